@@ -1,0 +1,247 @@
+#!/usr/bin/env python3
+"""Throughput of the eigenexpansion pressure solve on one MI355X.
+
+Default workload (vd128): 128^3 uniform grid, periodic x/y, walls in z,
+two-phase density (20 smoothed spheres, liquid 1000, gas 1-5) and Method-I
+splitting with rho0 = min(rho) computed on the device, FP64, 10 chained
+solves per step (p_prev <- p). One step = one such 10-solve chain; the
+metric counts grid points times solves per second.
+
+    python bench.py [--steps K] [--warmup W] [--workload vd128|mixed_tanh|fp64_tanh|const32]
+
+Prints one JSON line. Inputs are generated on the host (seeded), copied to
+the device and turned into f (discrete divergence) and rho (mixture rule) by
+the library before timing starts; the timed region holds only solves.
+
+The roofline object describes the kernel with the largest share of GPU time,
+measured with HIP events around each of its launches (psv_trace_*) in an
+eager pass of the same K steps on the launch stream. The CPU baseline is the
+FP64 oracle on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "pressure-solve grid pts/s + HBM GB/s % peak; mixed/batched vs FP64 GPU at fixed residual"
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    "vd128": dict(desc="128^3 uniform, Method I (rho0=min rho), 20 spheres, rho_l=1000, rho_g=1-5, "
+                       "10 chained solves per step", precision="fp64", n_steps=10),
+    "mixed_tanh": dict(desc="256x256x512 tanh-stretched z (alpha 1.5), Method I, 200 spheres, "
+                            "FP32 bulk + FP64 refinement to relres 1e-10", precision="mixed", n_steps=1),
+    "fp64_tanh": dict(desc="256x256x512 tanh-stretched z (alpha 1.5), Method I, 200 spheres, FP64",
+                      precision="fp64", n_steps=1),
+    "const32": dict(desc="32^3 uniform constant-coefficient solve, RHS = div(u) + cos mode",
+                    precision="fp64", n_steps=1),
+}
+
+
+def make_case(name):
+    import workloads as W
+    if name == "vd128":
+        return W.vd128()
+    if name in ("mixed_tanh", "fp64_tanh"):
+        return W.mixed_tanh()
+    if name == "const32":
+        return W.const32()
+    raise ValueError(name)
+
+
+def kernel_bytes(name, nx, ny, nz):
+    """Algorithmic HBM bytes of one launch: what the pass must read and write
+    at least (inputs once, outputs once; spectrum = (nx/2+1) ny nz complex)."""
+    n = nx * ny * nz
+    ns = (nx // 2 + 1) * ny * nz
+    c = 8 if name.endswith("fp32") else 16  # bytes per complex spectrum element
+    if name.startswith("fwd_x_method1"):
+        return 3 * 8 * n + c * ns
+    if name.startswith("fwd_x_resid"):
+        return 2 * 8 * n + c * ns
+    if name.startswith("fwd_x_const"):
+        return 8 * n + c * ns
+    if name.startswith(("fft_y", "thomas_z")):
+        return 2 * c * ns
+    if name.startswith("inv_x_add"):
+        return c * ns + 2 * 8 * n
+    if name.startswith("inv_x"):
+        return c * ns + 8 * n
+    if name == "min_rho":
+        return 8 * n
+    if name == "residual_fp64":
+        return 2 * 8 * n
+    return None
+
+
+def source_digest():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2005_11806_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(f.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch from committed rocprofv3 counter runs
+    (profiles/traffic_<kernel>_<workload>.json), if taken on the current
+    kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        t = json.load(fh)
+    if t.get("source_digest") != source_digest():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def blas_threads():
+    try:
+        from threadpoolctl import threadpool_info
+        n = [i["num_threads"] for i in threadpool_info() if i.get("user_api") == "blas"]
+        return max(n) if n else 1
+    except Exception:
+        return os.cpu_count() or 1
+
+
+def cpu_baseline(case, n_steps_target, budget_s=15.0):
+    """The FP64 oracle on the host: as many chained Method-I steps of the same
+    workload as fit in about budget_s seconds (at least one)."""
+    import oracle as O
+    g = O.Grid.from_spec(case.grid)
+    f = O.divergence_of_faces(*case.faces, g)
+    if case.extra_rhs is not None:
+        f = f + case.extra_rhs
+    rho = None if case.phi is None else O.mixture_density(case.phi, case.rho_gas, case.rho_liq)
+    t0 = time.perf_counter()
+    O.solve(f, g, rho, case.p_prev, n_steps=1, with_relres=False)
+    t1 = time.perf_counter() - t0
+    steps = 1
+    extra = int(max(0, min(n_steps_target - 1, (budget_s - t1) // max(t1, 1e-9))))
+    total = t1
+    if extra > 0:
+        t0 = time.perf_counter()
+        O.solve(f, g, rho, case.p_prev, n_steps=extra, with_relres=False)
+        total += time.perf_counter() - t0
+        steps += extra
+    return {"value": g.n * steps / total, "unit": "grid_pts/s", "cores": blas_threads(),
+            "kind": "oracle",
+            "sample": f"{steps} Method-I step(s) of the same grid and inputs "
+                      f"({g.nx}x{g.ny}x{g.nz}), matrix-form DFT + textbook Thomas, {total:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="vd128", choices=sorted(WORKLOADS))
+    ap.add_argument("--mode", default="graph", choices=["graph", "eager"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); this build has no "
+              "multi-GPU path", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2005_11806_amd as psv
+
+    wl = WORKLOADS[args.workload]
+    case = make_case(args.workload)
+    spec = case.grid
+    dev = torch.device("cuda:0")
+    to = lambda a: torch.from_numpy(a).to(dev)  # noqa: E731
+    const = case.phi is None
+    plan = psv.Plan(psv.Grid.from_spec(spec), precision=wl["precision"],
+                    method="const" if const else "method1")
+    f = plan.divergence(*(to(u) for u in case.faces))
+    if case.extra_rhs is not None:
+        f += to(case.extra_rhs)
+    rho = None if const else plan.density_from_colour(to(case.phi), to(case.rho_gas), case.rho_liq)
+    pp = None if const else to(case.p_prev)
+    out = torch.empty(spec.nz, spec.ny, spec.nx, dtype=torch.float64, device=dev)
+    n_steps = wl["n_steps"]
+
+    def step():
+        plan.solve(f, rho=rho, p_prev=pp, n_steps=n_steps, out=out)
+
+    # accuracy of the timed configuration (outside the timed region)
+    _, info = plan.solve(f, rho=rho, p_prev=pp, n_steps=n_steps, out=out, info=True)
+    mode = args.mode
+    if wl["precision"] == "mixed":
+        mode = "eager"  # the host-driven refinement loop synchronises to test convergence
+    graph = None
+    if mode == "graph":
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            step()
+        torch.cuda.current_stream().wait_stream(s)
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            step()
+        run = graph.replay
+    else:
+        run = step
+
+    for _ in range(args.warmup):
+        run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        run()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms = 1e3 * elapsed / args.steps
+    value = spec.n * n_steps * args.steps / elapsed
+
+    # per-kernel event timing over an eager pass of the same K steps
+    plan.trace(True)
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    summary = plan.trace_summary()
+    plan.trace(False)
+    dom = max(summary, key=lambda k: summary[k][1])
+    launches, total_ms = summary[dom]
+    avg_s = total_ms / launches * 1e-3
+    alg = kernel_bytes(dom, spec.nx, spec.ny, spec.nz)
+    achieved = alg / avg_s / 1e9 if alg else None
+    traffic = measured_traffic(dom, args.workload)
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": traffic,
+                "kernel": dom, "avg_launch_us": avg_s * 1e6, "algorithmic_bytes": alg,
+                "kernels": {k: {"launches": v[0], "avg_us": 1e3 * v[1] / v[0]} for k, v in
+                            sorted(summary.items(), key=lambda kv: -kv[1][1])}}
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(case, n_steps)
+
+    line = {
+        "metric": METRIC, "value": value, "unit": "grid_pts/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if wl["precision"] == "fp64" else "f32+f64",
+        "data": "synthetic (seeded generators in workloads/)",
+        "config": {"workload": f"{args.workload}: {wl['desc']}", "grid": [spec.nx, spec.ny, spec.nz],
+                   "solves_per_step": n_steps, "precision": wl["precision"], "mode": mode,
+                   "relres_last_solve": info.relres, "refine_steps": info.refine_steps},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,176 @@
+/*
+ * psv.h -- C ABI of the eigenexpansion pressure solve for variable-density
+ * two-phase flow (Dalla Barba et al., "An interface capturing method for
+ * liquid-gas flows at low-Mach number", arXiv:2005.11806).
+ *
+ * Problem (Sec. 3.3, Eq. lap_p): div(rho^-1 grad p) = f on a marker-and-cell
+ * grid (Sec. 3: p and all scalars at cell centres), periodic in x and y,
+ * walls in z where the pressure obeys the homogeneous Neumann condition that
+ * the eigenexpansion needs (Sec. 3.3.1). f is the user's right-hand side,
+ * i.e. (div u* - div u^{n+1}) / dt.
+ *
+ * Method I (Sec. 3.3.1, Eq. poisson_me1) recasts it with a constant
+ * coefficient; one step is
+ *     lap p^{s+1} = D[(1 - rho0/rho_face) G p^s] + rho0 f,   rho0 = min(rho),
+ * solved exactly by eigenexpansion: real FFT along x, FFT along y, one
+ * tridiagonal solve per wavenumber pair along z (uniform or stretched z),
+ * inverse FFTs, with the singular (0,0) mode projected (volume-weighted mean
+ * of the right-hand side removed) and gauged (volume-weighted mean of p = 0).
+ * The density on a face is the arithmetic mean of its two cells.
+ *
+ * Conventions for every call:
+ *  - Field pointers are DEVICE pointers to contiguous float64 arrays in
+ *    C order [nz][ny][nx] (x fastest), owned by the caller; the library
+ *    never frees or retains them beyond the call's stream work.
+ *  - `stream` is a hipStream_t (NULL = the default stream). Work is enqueued
+ *    asynchronously; a call returns before the GPU finishes unless it
+ *    documents a synchronisation.
+ *  - Arguments are validated on the host before anything is enqueued; a
+ *    non-OK status means nothing was enqueued (except PSV_ERR_HIP, and the
+ *    data-dependent checks of `check_inputs`, which synchronise).
+ *  - No exception crosses the ABI. psv_last_error_message() gives a
+ *    thread-local description of the last non-OK status.
+ *  - A plan owns one workspace: calls on one plan must not overlap in time
+ *    (serialise them on one stream).
+ */
+#ifndef PSV_H
+#define PSV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PSV_OK = 0,
+    PSV_ERR_INVALID_ARG = 1,      /* bad pointer, size, option or input value */
+    PSV_ERR_UNSUPPORTED_SIZE = 2, /* nx or ny not even or not 2^a 3^b, or too large */
+    PSV_ERR_HIP = 3,              /* a HIP runtime call failed */
+    PSV_ERR_NONFINITE = 4,        /* check_inputs found NaN/Inf in an input */
+    PSV_ERR_NOT_CONVERGED = 5,    /* mixed precision hit max_refine; p holds the last iterate */
+    PSV_ERR_OOM = 6               /* device or host allocation failed */
+} psv_status;
+
+typedef enum { PSV_FP64 = 0, PSV_MIXED = 1 } psv_precision;
+
+typedef enum {
+    PSV_CONST = 0,      /* constant coefficient: p = S(f), rho unused */
+    PSV_SPLIT_RHO0 = 1  /* Method I, Eq. poisson_me1 */
+} psv_method;
+
+typedef enum { PSV_BC_WALL_NEUMANN = 0 } psv_bc_z;
+
+/* Grid (Sec. 3). x and y periodic with nx, ny even and of the form 2^a 3^b,
+ * 4 <= nx, ny <= 1024; nz >= 2. zf: HOST array of nz+1 strictly increasing
+ * z-face positions with zf[0] = 0 and zf[nz] = lz (copied at plan creation),
+ * or NULL for uniform spacing lz/nz. Cell centres are face midpoints. */
+typedef struct {
+    int32_t nx, ny, nz;
+    double lx, ly, lz;
+    const double* zf;
+    psv_bc_z bc_z;
+} psv_grid;
+
+typedef struct {
+    psv_precision precision; /* FP64, or MIXED: FP32 transforms and tridiagonal
+                                sweeps, FP64 residual refinement */
+    psv_method method;
+    double tol;              /* MIXED: target relative residual; <= 0 selects 1e-10 */
+    int32_t max_refine;      /* MIXED: maximum refinement sweeps; <= 0 selects 4 */
+    int32_t check_inputs;    /* 1: scan inputs for NaN/Inf and rho <= 0 (synchronises) */
+    int32_t autotune;        /* 0: built-in launch shapes; 1: time candidates at plan creation */
+} psv_opts;
+
+typedef struct {
+    int32_t refine_steps;    /* refinement sweeps applied (MIXED) */
+    double relres;           /* ||r - L p||_2 / ||r||_2 of the last step, r = projected RHS */
+    double rhs_mean_removed; /* volume-weighted mean of the last step's RHS removed by projection */
+    double rho0_used;        /* the rho0 of the splitting */
+} psv_info;
+
+typedef struct psv_plan psv_plan;
+typedef struct psv_batch psv_batch;
+
+/* Fills *opts with the defaults (FP64, Method I, tol 1e-10, max_refine 4). */
+void psv_opts_default(psv_opts* opts);
+
+/* Host-only validation of a grid (no GPU needed). */
+psv_status psv_grid_validate(const psv_grid* grid);
+
+/* Builds the plan: validates, then allocates device tables (twiddles,
+ * eigenvalues lx[m] = -4 sin^2(pi m/nx)/dx^2 and ly, z-tridiagonal
+ * coefficients) and the workspace on the current device. */
+psv_status psv_plan_create(const psv_grid* grid, const psv_opts* opts, psv_plan** out);
+psv_status psv_plan_workspace_size(const psv_plan* plan, size_t* bytes);
+psv_status psv_plan_destroy(psv_plan* plan);
+
+/* One or more chained solves (Sec. 3.3.1, Eq. poisson_me1).
+ *  PSV_CONST:      p_out = S(f); rho and p_prev unused (may be NULL); n_steps must be 1.
+ *  PSV_SPLIT_RHO0: p_1 = S(rho0 f + D((1 - rho0/rho_f) G p_prev)), then n_steps-1 more
+ *                  steps with p_prev <- p; rho required; p_prev NULL means zero.
+ * rho0 > 0 is used as given; rho0 <= 0 selects min(rho), computed on the device.
+ * p_prev may alias p_out. If info != NULL the call synchronises `stream` and
+ * fills *info for the last step (relres is computed only then, or always in
+ * MIXED precision). */
+psv_status psv_solve(psv_plan* plan, const double* f, const double* rho, double rho0,
+                     const double* p_prev, double* p_out, int32_t n_steps, void* stream,
+                     psv_info* info);
+
+/* Adjoint of ONE Method-I step for loss = sum(w * p_out): gradients with respect
+ * to f, rho and p_prev (any output may be NULL to skip it). With rho0 > 0, rho0
+ * is an independent input: grad_rho is the partial derivative and
+ * d loss/d rho0 = sum(lambda f) - sum_faces gface/rho_f is written to
+ * *grad_rho0_host (f is then required). With rho0 <= 0 (rho0 = min rho),
+ * that derivative is added to grad_rho at the first cell holding the minimum
+ * (a subgradient), and also reported through grad_rho0_host if non-NULL.
+ * Synchronises `stream` only if grad_rho0_host != NULL. PSV_CONST plans return
+ * grad_f = S^T w and ignore the rest. */
+psv_status psv_solve_adjoint(psv_plan* plan, const double* w, const double* f, const double* rho,
+                             double rho0, const double* p_prev, double* grad_f, double* grad_rho,
+                             double* grad_p_prev, double* grad_rho0_host, void* stream);
+
+/* Mixture density of Sec. 2.2, Eq. eq_22, with the colour Phi = 1 in gas:
+ * rho = rho_gas * Phi + rho_liq * (1 - Phi). phi and rho_gas are device fields. */
+psv_status psv_density_from_colour(const psv_plan* plan, const double* phi, const double* rho_gas,
+                                   double rho_liq, double* rho_out, void* stream);
+
+/* Discrete divergence of a face field (the D of the 7-point operator):
+ * ux, uy [nz][ny][nx] hold the faces i+1/2 and j+1/2 (periodic), uz [nz+1][ny][nx]
+ * the z faces at zf[k] (uz[0] and uz[nz] are the wall values). */
+psv_status psv_divergence(const psv_plan* plan, const double* ux, const double* uy,
+                          const double* uz, double* div_out, void* stream);
+
+/* Relative residual ||r - L p||_2 / ||r - mean_V r||_2 of a constant-coefficient
+ * system, FP64 7-point operator; synchronises and writes *relres. */
+psv_status psv_relres(psv_plan* plan, const double* r, const double* p, void* stream,
+                      double* relres);
+
+/* Batched uneven problems (one grid per problem, x/y periodic, z walls) solved
+ * together: a persistent-kernel launch over a task queue, replayed from a
+ * captured HIP graph after the first call. Pointer arrays are HOST arrays
+ * of DEVICE pointers; rho0 is a HOST array (<= 0 selects min(rho)). */
+psv_status psv_batch_create(int32_t n, const psv_grid* grids, const psv_opts* opts,
+                            psv_batch** out);
+psv_status psv_batch_solve(psv_batch* batch, const double* const* f, const double* const* rho,
+                           const double* rho0, const double* const* p_prev, double* const* p_out,
+                           void* stream, psv_info* infos);
+psv_status psv_batch_destroy(psv_batch* batch);
+
+/* Per-kernel timing (profiling aid): with enable = 1 every kernel the plan
+ * launches is bracketed by two hipEvents on its launch stream.
+ * psv_trace_summary synchronises on the recorded events, writes a JSON object
+ * {"kernel": [launches, total_ms], ...} (NUL-terminated, truncated to `len`)
+ * into buf, stores the untruncated length in *needed (may be NULL) and
+ * clears the records. */
+psv_status psv_trace_enable(psv_plan* plan, int32_t enable);
+psv_status psv_trace_summary(psv_plan* plan, char* buf, size_t len, size_t* needed);
+
+const char* psv_status_string(psv_status s);
+const char* psv_last_error_message(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PSV_H */

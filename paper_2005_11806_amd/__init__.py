@@ -1,0 +1,225 @@
+"""MI355X-native eigenexpansion pressure solve for variable-density two-phase
+flow (Dalla Barba et al., arXiv:2005.11806, Sec. 3.3.1).
+
+Thin Python binding over libpsv.so (include/psv.h): every step of the solve
+runs in the library's HIP kernels; this module only checks tensors and passes
+their device pointers. PyTorch provides device memory and streams.
+
+    import paper_2005_11806_amd as psv
+    plan = psv.Plan(psv.Grid(128, 128, 128, 1.0, 1.0, 1.0))
+    p = plan.solve(f, rho=rho, p_prev=p_prev, n_steps=10)
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+
+import numpy as np
+
+from . import _abi
+from ._abi import PsvError, check
+
+__all__ = ["Grid", "Plan", "SolveInfo", "PsvError", "lib", "PressureSolve", "pressure_solve"]
+
+
+def lib():
+    return _abi.load()
+
+
+@dataclasses.dataclass
+class Grid:
+    """Periodic x, y; walls in z. zf: nz+1 face positions (0 .. lz) or None (uniform)."""
+    nx: int
+    ny: int
+    nz: int
+    lx: float = 1.0
+    ly: float = 1.0
+    lz: float = 1.0
+    zf: object = None
+
+    @classmethod
+    def from_spec(cls, spec):
+        return cls(spec.nx, spec.ny, spec.nz, spec.lx, spec.ly, spec.lz, spec.zf)
+
+    def _c(self):
+        g = _abi.psv_grid()
+        g.nx, g.ny, g.nz = int(self.nx), int(self.ny), int(self.nz)
+        g.lx, g.ly, g.lz = float(self.lx), float(self.ly), float(self.lz)
+        keep = None
+        if self.zf is not None:
+            keep = np.ascontiguousarray(np.asarray(self.zf, dtype=np.float64))
+            g.zf = keep.ctypes.data_as(_abi.dptr)
+        else:
+            g.zf = None
+        g.bc_z = _abi.PSV_BC_WALL_NEUMANN
+        return g, keep
+
+    @property
+    def shape(self):
+        return (self.nz, self.ny, self.nx)
+
+    def validate(self):
+        g, _keep = self._c()
+        check(lib().psv_grid_validate(C.byref(g)))
+
+
+@dataclasses.dataclass
+class SolveInfo:
+    refine_steps: int
+    relres: float
+    rhs_mean_removed: float
+    rho0_used: float
+
+
+_PREC = {"fp64": _abi.PSV_FP64, "mixed": _abi.PSV_MIXED}
+_METH = {"const": _abi.PSV_CONST, "method1": _abi.PSV_SPLIT_RHO0}
+
+
+def _ptr(t, shape=None, name="tensor"):
+    """Device pointer of a contiguous float64 CUDA tensor (None -> NULL)."""
+    if t is None:
+        return None
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.dtype != torch.float64:
+        raise TypeError(f"{name} must be float64")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+class Plan:
+    """A solver plan: device tables and workspace for one grid.
+
+    precision: "fp64" or "mixed" (FP32 transforms/tridiagonal + FP64 refinement);
+    method: "method1" (Eq. poisson_me1 with rho0 = min rho) or "const".
+    """
+
+    def __init__(self, grid: Grid, precision="fp64", method="method1", tol=1e-10,
+                 max_refine=4, check_inputs=False, autotune=0):
+        self.grid = grid
+        self.precision = precision
+        self.method = method
+        o = _abi.psv_opts()
+        lib().psv_opts_default(C.byref(o))
+        o.precision = _PREC[precision]
+        o.method = _METH[method]
+        o.tol = float(tol)
+        o.max_refine = int(max_refine)
+        o.check_inputs = int(bool(check_inputs))
+        o.autotune = int(autotune)
+        g, _keep = grid._c()
+        h = C.c_void_p()
+        check(lib().psv_plan_create(C.byref(g), C.byref(o), C.byref(h)))
+        self._h = h
+
+    @property
+    def shape(self):
+        return self.grid.shape
+
+    def workspace_size(self) -> int:
+        n = C.c_size_t()
+        check(lib().psv_plan_workspace_size(self._h, C.byref(n)))
+        return n.value
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            check(lib().psv_plan_destroy(self._h))
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, f, rho=None, p_prev=None, rho0=None, n_steps=1, out=None, stream=None,
+              info=False):
+        import torch
+        sh = self.shape
+        if out is None:
+            out = torch.empty(sh, dtype=torch.float64, device=f.device)
+        inf = _abi.psv_info() if info else None
+        st = lib().psv_solve(self._h, _ptr(f, sh, "f"), _ptr(rho, sh, "rho"),
+                             0.0 if rho0 is None else float(rho0), _ptr(p_prev, sh, "p_prev"),
+                             _ptr(out, sh, "out"), int(n_steps), _stream(stream),
+                             C.byref(inf) if info else None)
+        if info:
+            si = SolveInfo(inf.refine_steps, inf.relres, inf.rhs_mean_removed, inf.rho0_used)
+            if st == _abi.PSV_ERR_NOT_CONVERGED:
+                raise PsvError(st, f"not converged: {si}")
+            check(st)
+            return out, si
+        check(st)
+        return out
+
+    def adjoint(self, w, f=None, rho=None, p_prev=None, rho0=None, grad_f=True, grad_rho=True,
+                grad_p_prev=False, grad_rho0=False, stream=None):
+        """Gradients of sum(w * p) for one step; returns a dict of tensors
+        (and 'rho0' as a float when grad_rho0)."""
+        import torch
+        sh = self.shape
+        mk = lambda want: torch.empty(sh, dtype=torch.float64, device=w.device) if want else None  # noqa
+        gf, gr, gp = mk(grad_f), mk(grad_rho), mk(grad_p_prev)
+        r0 = C.c_double(0.0)
+        check(lib().psv_solve_adjoint(self._h, _ptr(w, sh, "w"), _ptr(f, sh, "f"), _ptr(rho, sh, "rho"),
+                                      0.0 if rho0 is None else float(rho0), _ptr(p_prev, sh, "p_prev"),
+                                      _ptr(gf, sh), _ptr(gr, sh), _ptr(gp, sh),
+                                      C.byref(r0) if grad_rho0 else None, _stream(stream)))
+        out = {"f": gf, "rho": gr, "p_prev": gp}
+        if grad_rho0:
+            out["rho0"] = r0.value
+        return out
+
+    def density_from_colour(self, phi, rho_gas, rho_liq, out=None, stream=None):
+        import torch
+        sh = self.shape
+        if out is None:
+            out = torch.empty(sh, dtype=torch.float64, device=phi.device)
+        check(lib().psv_density_from_colour(self._h, _ptr(phi, sh, "phi"), _ptr(rho_gas, sh, "rho_gas"),
+                                            float(rho_liq), _ptr(out, sh, "out"), _stream(stream)))
+        return out
+
+    def divergence(self, ux, uy, uz, out=None, stream=None):
+        import torch
+        nz, ny, nx = self.shape
+        if out is None:
+            out = torch.empty(self.shape, dtype=torch.float64, device=ux.device)
+        check(lib().psv_divergence(self._h, _ptr(ux, self.shape, "ux"), _ptr(uy, self.shape, "uy"),
+                                   _ptr(uz, (nz + 1, ny, nx), "uz"), _ptr(out, self.shape, "out"),
+                                   _stream(stream)))
+        return out
+
+    def trace(self, enable=True):
+        """Per-kernel HIP-event timing of this plan's launches."""
+        check(lib().psv_trace_enable(self._h, int(bool(enable))))
+
+    def trace_summary(self) -> dict:
+        """{kernel: (launches, total_ms)} since the last summary (synchronises)."""
+        import json
+        need = C.c_size_t()
+        buf = C.create_string_buffer(1 << 16)
+        check(lib().psv_trace_summary(self._h, buf, len(buf), C.byref(need)))
+        if need.value > len(buf):
+            raise RuntimeError("trace summary truncated")
+        return {k: (int(v[0]), float(v[1])) for k, v in json.loads(buf.value.decode()).items()}
+
+    def relres(self, r, p, stream=None) -> float:
+        v = C.c_double()
+        check(lib().psv_relres(self._h, _ptr(r, self.shape, "r"), _ptr(p, self.shape, "p"),
+                               _stream(stream), C.byref(v)))
+        return v.value
+
+
+from .autograd import PressureSolve, pressure_solve  # noqa: E402

@@ -1,0 +1,389 @@
+// C-ABI entry points of libpsv (declared in include/psv.h). Every entry point
+// validates on the host first, then enqueues the kernel sequence of the
+// eigenexpansion solve on the caller's stream. Exceptions never cross the ABI.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "internal.hpp"
+
+namespace psv {
+void validate_grid(const psv_grid* g);
+void validate_opts(const psv_opts* o);
+void default_opts(psv_opts* o);
+std::string trace_summary(Plan& p);
+void trace_free(Plan& p);
+}  // namespace psv
+
+struct psv_plan {
+    psv::Plan p;
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+psv_status ok() { return PSV_OK; }
+
+psv_status record(psv_status s, const std::string& msg) {
+    g_last_error = msg;
+    return s;
+}
+
+template <typename F>
+psv_status guarded(F&& fn) {
+    try {
+        fn();
+        return ok();
+    } catch (const psv::Error& e) {
+        return record(e.status, e.msg);
+    } catch (const std::bad_alloc&) {
+        return record(PSV_ERR_OOM, "host allocation failed");
+    } catch (...) {
+        return record(PSV_ERR_HIP, "unexpected internal error");
+    }
+}
+
+void need(bool cond, const char* msg) {
+    if (!cond) psv::fail(PSV_ERR_INVALID_ARG, msg);
+}
+
+using psv::Plan;
+
+void sync_read(const Plan& P, hipStream_t s) {
+    PSV_HIP(hipMemcpyAsync(P.host_scal, P.scal, psv::S_NSCAL * sizeof(double), hipMemcpyDeviceToHost, s));
+    PSV_HIP(hipMemcpyAsync(P.host_flags, P.flags, psv::F_NFLAG * sizeof(int), hipMemcpyDeviceToHost, s));
+    PSV_HIP(hipStreamSynchronize(s));
+}
+
+// Data-dependent input checks (synchronising); flags[F_STEPS] is used as scratch.
+void check_field(const Plan& P, const double* x, bool positive, const char* name, hipStream_t s) {
+    if (!x) return;
+    int* bad = P.flags + psv::F_STEPS;
+    PSV_HIP(hipMemsetAsync(bad, 0, sizeof(int), s));
+    psv::launch_scan_inputs(P, x, positive ? 1 : 0, bad, s);
+    sync_read(P, s);
+    const int b = P.host_flags[psv::F_STEPS];
+    if (b & 1) psv::fail(PSV_ERR_NONFINITE, std::string(name) + " holds NaN or Inf");
+    if (b & 2) psv::fail(PSV_ERR_INVALID_ARG, std::string(name) + " must be > 0 everywhere");
+}
+
+// One constant-coefficient solve of the system assembled by `a` (CONST or
+// METHOD1), written to `out`. FP64: five passes. MIXED: the same passes in
+// FP32 followed by FP64 residual refinement until relres <= tol. Returns the
+// number of refinement sweeps (MIXED) and leaves relres in scal[S_RELRES]
+// when it was computed.
+struct CoreResult {
+    int steps = 0;
+    bool converged = true;
+    bool have_relres = false;
+};
+
+CoreResult solve_core(Plan& P, psv::FwdArgs a, double* out, bool want_relres, hipStream_t s) {
+    using namespace psv;
+    const bool mixed = P.opts.precision == PSV_MIXED;
+    const double inv_scale = 2.0 / ((double)P.nx * P.ny);
+    CoreResult res;
+    a.r_out = (mixed || want_relres) ? P.r_ws : nullptr;
+    a.done = nullptr;
+    // MIXED: the mean removed by the projection is taken in FP64 from the
+    // assembly pass; the one the FP32 (0,0) column yields is discarded.
+    a.partials = mixed ? P.partials : nullptr;
+    launch_fwd_x(P, mixed, a, s);
+    if (mixed) launch_mean_finalize(P, fwd_x_blocks(P), P.scal + S_RHS_MEAN, s);
+    launch_fft_y(P, mixed, false, nullptr, s);
+    launch_thomas(P, mixed, P.scal + (mixed ? S_MEAN2 : S_RHS_MEAN), nullptr, s);
+    launch_fft_y(P, mixed, true, nullptr, s);
+    launch_inv_x(P, mixed, INV_STORE, out, inv_scale, nullptr, s);
+    if (!mixed) {
+        if (want_relres) {
+            launch_residual(P, P.r_ws, out, P.scal + S_RHS_MEAN, s);
+            res.have_relres = true;
+        }
+        return res;
+    }
+    FwdArgs ra{};
+    ra.mode = FWD_RESID;
+    ra.r_in = P.r_ws;
+    ra.pprev = out;
+    ra.mean = P.scal + S_RHS_MEAN;
+    ra.partials = P.partials;
+    bool fused = true;
+    res.have_relres = true;
+    for (;;) {
+        if (fused) {
+            launch_fwd_x(P, true, ra, s);
+            launch_norm_finalize(P, fwd_x_blocks(P), 0.0, s);
+        } else {
+            launch_residual(P, P.r_ws, out, P.scal + S_RHS_MEAN, s);
+        }
+        sync_read(P, s);
+        const double rr = P.host_scal[S_RELRES];
+        if (rr <= P.opts.tol) {
+            res.converged = true;
+            break;
+        }
+        if (res.steps >= P.opts.max_refine || !std::isfinite(rr)) {
+            res.converged = false;
+            break;
+        }
+        if (!fused) {
+            launch_fwd_x(P, true, ra, s);
+        }
+        launch_fft_y(P, true, false, nullptr, s);
+        launch_thomas(P, true, P.scal + S_MEAN2, nullptr, s);
+        launch_fft_y(P, true, true, nullptr, s);
+        launch_inv_x(P, true, INV_ADD, out, inv_scale, nullptr, s);
+        res.steps++;
+        fused = false;
+    }
+    return res;
+}
+
+}  // namespace
+
+extern "C" {
+
+void psv_opts_default(psv_opts* opts) {
+    if (opts) psv::default_opts(opts);
+}
+
+psv_status psv_grid_validate(const psv_grid* grid) {
+    return guarded([&] { psv::validate_grid(grid); });
+}
+
+psv_status psv_plan_create(const psv_grid* grid, const psv_opts* opts, psv_plan** out) {
+    return guarded([&] {
+        need(out != nullptr, "out is NULL");
+        *out = nullptr;
+        psv::validate_grid(grid);
+        psv::validate_opts(opts);
+        psv_opts o;
+        if (opts)
+            o = *opts;
+        else
+            psv::default_opts(&o);
+        auto* pl = new psv_plan();
+        try {
+            psv::plan_init(pl->p, *grid, o, true);
+        } catch (...) {
+            psv::plan_free(pl->p);
+            delete pl;
+            throw;
+        }
+        *out = pl;
+    });
+}
+
+psv_status psv_plan_workspace_size(const psv_plan* plan, size_t* bytes) {
+    return guarded([&] {
+        need(plan && bytes, "plan and bytes must be non-NULL");
+        *bytes = plan->p.ws_bytes;
+    });
+}
+
+psv_status psv_plan_destroy(psv_plan* plan) {
+    return guarded([&] {
+        if (!plan) return;
+        psv::trace_free(plan->p);
+        psv::plan_free(plan->p);
+        delete plan;
+    });
+}
+
+psv_status psv_solve(psv_plan* plan, const double* f, const double* rho, double rho0,
+                     const double* p_prev, double* p_out, int32_t n_steps, void* stream,
+                     psv_info* info) {
+    return guarded([&] {
+        need(plan != nullptr, "plan is NULL");
+        need(f != nullptr, "f is NULL");
+        need(p_out != nullptr, "p_out is NULL");
+        need(n_steps >= 1, "n_steps must be >= 1");
+        need(std::isfinite(rho0), "rho0 must be finite");
+        Plan& P = plan->p;
+        const bool method1 = P.opts.method == PSV_SPLIT_RHO0;
+        if (method1)
+            need(rho != nullptr, "rho is required by Method I");
+        else
+            need(n_steps == 1, "the constant-coefficient solve takes n_steps = 1");
+        hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+        PSV_HIP(hipSetDevice(P.device));
+        if (P.opts.check_inputs) {
+            check_field(P, f, false, "f", s);
+            if (method1) check_field(P, rho, true, "rho", s);
+            if (method1) check_field(P, p_prev, false, "p_prev", s);
+        }
+        psv::FwdArgs a{};
+        a.f = f;
+        a.rho = rho;
+        a.rho0 = P.scal + psv::S_RHO0;
+        if (method1) {
+            if (rho0 > 0.0)
+                psv::launch_set_scalar(P.scal + psv::S_RHO0, rho0, s);
+            else
+                psv::launch_min_reduce(P, rho, P.scal + psv::S_RHO0, P.flags + psv::F_ARGMIN, s);
+            if (P.opts.check_inputs && rho0 > 0.0) {
+                psv::launch_min_reduce(P, rho, P.scal + psv::S_MEAN2, nullptr, s);
+                sync_read(P, s);
+                if (rho0 > P.host_scal[psv::S_MEAN2])
+                    psv::fail(PSV_ERR_INVALID_ARG, "rho0 exceeds min(rho): the splitting does not contract");
+            }
+            if (!p_prev) {
+                psv::launch_fill(p_out, P.ncell(), 0.0, s);
+                p_prev = p_out;
+            }
+        } else {
+            psv::launch_set_scalar(P.scal + psv::S_RHO0, 0.0, s);
+        }
+        a.mode = method1 ? psv::FWD_METHOD1 : psv::FWD_CONST;
+        CoreResult cr;
+        int total_steps = 0;
+        for (int step = 0; step < n_steps; ++step) {
+            a.pprev = (step == 0) ? p_prev : p_out;
+            const bool last = step + 1 == n_steps;
+            cr = solve_core(P, a, p_out, last && info != nullptr, s);
+            total_steps += cr.steps;
+            if (!cr.converged) {
+                if (info) {
+                    sync_read(P, s);
+                    info->refine_steps = total_steps;
+                    info->relres = P.host_scal[psv::S_RELRES];
+                    info->rhs_mean_removed = P.host_scal[psv::S_RHS_MEAN];
+                    info->rho0_used = P.host_scal[psv::S_RHO0];
+                }
+                psv::fail(PSV_ERR_NOT_CONVERGED, "mixed-precision refinement reached max_refine");
+            }
+        }
+        if (info) {
+            sync_read(P, s);
+            info->refine_steps = total_steps;
+            info->relres = cr.have_relres ? P.host_scal[psv::S_RELRES] : NAN;
+            info->rhs_mean_removed = P.host_scal[psv::S_RHS_MEAN];
+            info->rho0_used = P.host_scal[psv::S_RHO0];
+        }
+    });
+}
+
+psv_status psv_solve_adjoint(psv_plan* plan, const double* w, const double* f, const double* rho,
+                             double rho0, const double* p_prev, double* grad_f, double* grad_rho,
+                             double* grad_p_prev, double* grad_rho0_host, void* stream) {
+    return guarded([&] {
+        need(plan != nullptr, "plan is NULL");
+        need(w != nullptr, "w is NULL");
+        need(std::isfinite(rho0), "rho0 must be finite");
+        Plan& P = plan->p;
+        const bool method1 = P.opts.method == PSV_SPLIT_RHO0;
+        hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+        PSV_HIP(hipSetDevice(P.device));
+        double* x = P.r_ws + P.ncell();  // S(V^-1 w)
+        psv::FwdArgs a{};
+        a.mode = psv::FWD_CONST;
+        a.f = w;
+        a.scale = P.t.inv_vol;
+        CoreResult cr = solve_core(P, a, x, false, s);
+        if (!cr.converged) psv::fail(PSV_ERR_NOT_CONVERGED, "mixed-precision refinement reached max_refine");
+        if (!method1) {
+            if (grad_f) psv::launch_scale_vol(P, x, grad_f, s);
+            return;
+        }
+        need(rho != nullptr && p_prev != nullptr, "Method I adjoint needs rho and p_prev");
+        const bool want_r0 = grad_rho0_host != nullptr || (rho0 <= 0.0 && grad_rho != nullptr);
+        if (want_r0) need(f != nullptr, "f is required for the rho0 derivative");
+        if (rho0 > 0.0)
+            psv::launch_set_scalar(P.scal + psv::S_RHO0, rho0, s);
+        else
+            psv::launch_min_reduce(P, rho, P.scal + psv::S_RHO0, P.flags + psv::F_ARGMIN, s);
+        psv::launch_adjoint_faces(P, x, f, rho, p_prev, P.scal + psv::S_RHO0, grad_f, grad_rho,
+                                  grad_p_prev, P.partials, s);
+        psv::launch_adjoint_finalize(P, psv::adjoint_blocks(P), grad_rho,
+                                     (rho0 <= 0.0 && f != nullptr) ? 1 : 0, s);
+        if (grad_rho0_host) {
+            sync_read(P, s);
+            *grad_rho0_host = P.host_scal[psv::S_GRAD_RHO0];
+        }
+    });
+}
+
+psv_status psv_density_from_colour(const psv_plan* plan, const double* phi, const double* rho_gas,
+                                   double rho_liq, double* rho_out, void* stream) {
+    return guarded([&] {
+        need(plan && phi && rho_gas && rho_out, "plan, phi, rho_gas and rho_out must be non-NULL");
+        need(std::isfinite(rho_liq) && rho_liq > 0.0, "rho_liq must be positive and finite");
+        PSV_HIP(hipSetDevice(plan->p.device));
+        psv::launch_density(plan->p, phi, rho_gas, rho_liq, rho_out, reinterpret_cast<hipStream_t>(stream));
+    });
+}
+
+psv_status psv_divergence(const psv_plan* plan, const double* ux, const double* uy,
+                          const double* uz, double* div_out, void* stream) {
+    return guarded([&] {
+        need(plan && ux && uy && uz && div_out, "all pointers must be non-NULL");
+        PSV_HIP(hipSetDevice(plan->p.device));
+        psv::launch_divergence(plan->p, ux, uy, uz, div_out, reinterpret_cast<hipStream_t>(stream));
+    });
+}
+
+psv_status psv_relres(psv_plan* plan, const double* r, const double* p, void* stream,
+                      double* relres) {
+    return guarded([&] {
+        need(plan && r && p && relres, "all pointers must be non-NULL");
+        Plan& P = plan->p;
+        hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+        PSV_HIP(hipSetDevice(P.device));
+        psv::launch_vmean(P, r, P.scal + psv::S_MEAN2, s);
+        psv::launch_residual(P, r, p, P.scal + psv::S_MEAN2, s);
+        sync_read(P, s);
+        *relres = P.host_scal[psv::S_RELRES];
+    });
+}
+
+psv_status psv_batch_create(int32_t, const psv_grid*, const psv_opts*, psv_batch** out) {
+    if (out) *out = nullptr;
+    return record(PSV_ERR_INVALID_ARG, "batched solves are not available in this build");
+}
+
+psv_status psv_batch_solve(psv_batch*, const double* const*, const double* const*, const double*,
+                           const double* const*, double* const*, void*, psv_info*) {
+    return record(PSV_ERR_INVALID_ARG, "batched solves are not available in this build");
+}
+
+psv_status psv_batch_destroy(psv_batch*) { return PSV_OK; }
+
+psv_status psv_trace_enable(psv_plan* plan, int32_t enable) {
+    return guarded([&] {
+        need(plan != nullptr, "plan is NULL");
+        plan->p.trace.on = enable != 0;
+    });
+}
+
+psv_status psv_trace_summary(psv_plan* plan, char* buf, size_t len, size_t* needed) {
+    return guarded([&] {
+        need(plan != nullptr, "plan is NULL");
+        need(buf != nullptr || len == 0, "buf is NULL");
+        const std::string s = psv::trace_summary(plan->p);
+        if (needed) *needed = s.size() + 1;
+        if (len > 0) {
+            const size_t n = std::min(len - 1, s.size());
+            std::memcpy(buf, s.data(), n);
+            buf[n] = '\0';
+        }
+    });
+}
+
+const char* psv_status_string(psv_status s) {
+    switch (s) {
+        case PSV_OK: return "PSV_OK";
+        case PSV_ERR_INVALID_ARG: return "PSV_ERR_INVALID_ARG";
+        case PSV_ERR_UNSUPPORTED_SIZE: return "PSV_ERR_UNSUPPORTED_SIZE";
+        case PSV_ERR_HIP: return "PSV_ERR_HIP";
+        case PSV_ERR_NONFINITE: return "PSV_ERR_NONFINITE";
+        case PSV_ERR_NOT_CONVERGED: return "PSV_ERR_NOT_CONVERGED";
+        case PSV_ERR_OOM: return "PSV_ERR_OOM";
+    }
+    return "PSV_ERR_UNKNOWN";
+}
+
+const char* psv_last_error_message(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

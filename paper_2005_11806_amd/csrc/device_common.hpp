@@ -1,0 +1,178 @@
+// Device-side building blocks shared by the kernels of libpsv: complex
+// arithmetic on HIP vector types, butterflies and a Stockham autosort FFT
+// over batches of lines held in LDS.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace psv {
+
+template <typename T> struct V2;
+template <> struct V2<double> { using t = double2; };
+template <> struct V2<float> { using t = float2; };
+template <typename T> using c2 = typename V2<T>::t;
+
+template <typename C>
+__device__ __forceinline__ C cadd(C a, C b) { return C{a.x + b.x, a.y + b.y}; }
+template <typename C>
+__device__ __forceinline__ C csub(C a, C b) { return C{a.x - b.x, a.y - b.y}; }
+template <typename C>
+__device__ __forceinline__ C cmul(C a, C b) { return C{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
+template <typename C>
+__device__ __forceinline__ C cconj(C a) { return C{a.x, -a.y}; }
+template <typename C, typename T>
+__device__ __forceinline__ C cscale(C a, T s) { return C{a.x * s, a.y * s}; }
+// multiply by (sign * i): sign = -1 gives -i, +1 gives +i
+template <int SIGN, typename C>
+__device__ __forceinline__ C cmul_i(C a) {
+    return SIGN > 0 ? C{-a.y, a.x} : C{a.y, -a.x};
+}
+
+template <typename D, typename S>
+__device__ __forceinline__ D cconv(S a) { return D{(decltype(D::x))a.x, (decltype(D::x))a.y}; }
+
+// Radix sequence of one FFT length (product of r[0..count-1] = n).
+struct Radices {
+    int n;
+    int count;
+    int r[12];
+};
+
+// ---------------------------------------------------------------------------
+// DFT of R points in registers: V[q] = sum_r v[r] exp(DIR 2 pi i r q / R).
+template <int DIR, typename C>
+__device__ __forceinline__ void bfly2(C* v) {
+    C a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+}
+
+template <int DIR, typename C>
+__device__ __forceinline__ void bfly4(C* v) {
+    C t0 = cadd(v[0], v[2]);
+    C t1 = csub(v[0], v[2]);
+    C t2 = cadd(v[1], v[3]);
+    C t3 = cmul_i<DIR>(csub(v[1], v[3]));
+    v[0] = cadd(t0, t2);
+    v[2] = csub(t0, t2);
+    v[1] = cadd(t1, t3);
+    v[3] = csub(t1, t3);
+}
+
+template <int DIR, typename C>
+__device__ __forceinline__ void bfly3(C* v) {
+    using T = decltype(C::x);
+    const T half_sqrt3 = (T)0.86602540378443864676372317075294;
+    C s = cadd(v[1], v[2]);
+    C d = csub(v[1], v[2]);
+    C m = C{v[0].x - (T)0.5 * s.x, v[0].y - (T)0.5 * s.y};
+    C rot = cmul_i<DIR>(cscale(d, half_sqrt3));
+    v[0] = cadd(v[0], s);
+    v[1] = cadd(m, rot);
+    v[2] = csub(m, rot);
+}
+
+template <int DIR, typename C>
+__device__ __forceinline__ void bfly8(C* v) {
+    using T = decltype(C::x);
+    const T rs2 = (T)0.70710678118654752440084436210485;
+    C e[4] = {v[0], v[2], v[4], v[6]};
+    C o[4] = {v[1], v[3], v[5], v[7]};
+    bfly4<DIR>(e);
+    bfly4<DIR>(o);
+    // w8^q = exp(DIR 2 pi i q / 8)
+    C o1 = C{(o[1].x - (T)DIR * o[1].y) * rs2, ((T)DIR * o[1].x + o[1].y) * rs2};   // * (1 + DIR i)/sqrt2
+    C o2 = cmul_i<DIR>(o[2]);                                                         // * DIR i
+    C o3 = C{(-o[3].x - (T)DIR * o[3].y) * rs2, ((T)DIR * o[3].x - o[3].y) * rs2};  // * (-1 + DIR i)/sqrt2
+    v[0] = cadd(e[0], o[0]);
+    v[4] = csub(e[0], o[0]);
+    v[1] = cadd(e[1], o1);
+    v[5] = csub(e[1], o1);
+    v[2] = cadd(e[2], o2);
+    v[6] = csub(e[2], o2);
+    v[3] = cadd(e[3], o3);
+    v[7] = csub(e[3], o3);
+}
+
+// One Stockham stage for butterfly j of a line: reads R points at stride L/R,
+// twiddles by W^(r k) with W = exp(DIR 2 pi i / (Ns R)), k = j mod Ns, and
+// writes them to (j / Ns) Ns R + k + r Ns. `tw` holds exp(-2 pi i t / twn).
+template <int R, int DIR, typename C>
+__device__ __forceinline__ void stockham_bfly(const C* __restrict__ in, C* __restrict__ out, int j,
+                                              int nb, int Ns, const C* __restrict__ tw, int tstep) {
+    C v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = in[j + r * nb];
+    const int k = j % Ns;
+    if (Ns > 1) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+            C w = tw[r * k * tstep];
+            if (DIR > 0) w.y = -w.y;
+            v[r] = cmul(v[r], w);
+        }
+    }
+    if (R == 2) bfly2<DIR>(v);
+    if (R == 3) bfly3<DIR>(v);
+    if (R == 4) bfly4<DIR>(v);
+    if (R == 8) bfly8<DIR>(v);
+    const int base = (j / Ns) * Ns * R + k;
+#pragma unroll
+    for (int r = 0; r < R; ++r) out[base + r * Ns] = v[r];
+}
+
+// Unnormalised FFT of `nlines` lines of length L stored in LDS at buf0 +
+// line * lstride, ping-ponging with buf1. All threads of the block take part;
+// returns the buffer that holds the result. Twiddles come from a table of
+// exp(-2 pi i t / twn) with twn a multiple of L.
+template <int DIR, typename C>
+__device__ C* lds_fft(C* buf0, C* buf1, int L, int nlines, int lstride, const Radices& rp,
+                      const C* __restrict__ tw, int twn) {
+    C* src = buf0;
+    C* dst = buf1;
+    int Ns = 1;
+    const int tid = threadIdx.x;
+    const int nthr = blockDim.x;
+    for (int s = 0; s < rp.count; ++s) {
+        const int R = rp.r[s];
+        const int nb = L / R;
+        const int total = nlines * nb;
+        const int tstep = twn / (Ns * R);
+        for (int t = tid; t < total; t += nthr) {
+            const int line = t / nb;
+            const int j = t - line * nb;
+            const C* in = src + line * lstride;
+            C* out = dst + line * lstride;
+            switch (R) {
+                case 2: stockham_bfly<2, DIR>(in, out, j, nb, Ns, tw, tstep); break;
+                case 3: stockham_bfly<3, DIR>(in, out, j, nb, Ns, tw, tstep); break;
+                case 4: stockham_bfly<4, DIR>(in, out, j, nb, Ns, tw, tstep); break;
+                default: stockham_bfly<8, DIR>(in, out, j, nb, Ns, tw, tstep); break;
+            }
+        }
+        __syncthreads();
+        C* t = src;
+        src = dst;
+        dst = t;
+        Ns *= R;
+    }
+    return src;
+}
+
+// Block-wide sum of one double per thread (blockDim.x <= 1024, multiple of 64).
+__device__ inline double block_sum(double v, double* sh) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sh[wid] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0) {
+        const int nw = (blockDim.x + 63) >> 6;
+        for (int w = 0; w < nw; ++w) s += sh[w];
+    }
+    return s;  // valid on thread 0
+}
+
+}  // namespace psv

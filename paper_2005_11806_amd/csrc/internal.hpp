@@ -1,0 +1,184 @@
+// Host-side internals of libpsv: the plan, launch parameters and the kernel
+// launchers implemented in the .hip translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/psv.h"
+#include "device_common.hpp"
+
+namespace psv {
+
+// Error carrying a psv_status; caught at the C-ABI boundary.
+struct Error {
+    psv_status status;
+    std::string msg;
+};
+
+[[noreturn]] void fail(psv_status s, const std::string& msg);
+void hip_check(hipError_t e, const char* what);
+#define PSV_HIP(call) ::psv::hip_check((call), #call)
+
+// Radix sequence of a 2^a 3^b length (8s, then 4 / 2, then 3s).
+Radices make_radices(int n);
+
+// Assembly modes of the forward x pass.
+enum FwdMode : int {
+    FWD_CONST = 0,    // r = f * scale[k] (scale may be null)
+    FWD_METHOD1 = 1,  // r = rho0 f + D((1 - rho0/rho_f) G p_prev)
+    FWD_RESID = 2     // r = r_in - mean - L p (refinement residual), norm partials
+};
+// Store modes of the inverse x pass.
+enum InvMode : int {
+    INV_STORE = 0,  // p = x
+    INV_ADD = 1,    // p += x
+    INV_SCALE = 2   // p = x * vol[k]
+};
+
+// Device-resident scalars of a plan (offsets into Plan::scal).
+enum Scalar : int {
+    S_RHO0 = 0,
+    S_RHS_MEAN = 1,
+    S_RES2 = 2,
+    S_R2 = 3,
+    S_RELRES = 4,
+    S_GRAD_RHO0 = 5,
+    S_MEAN2 = 6,       // mean removed by a refinement solve (discarded)
+    S_NSCAL = 16
+};
+enum Flag : int { F_DONE = 0, F_ARGMIN = 1, F_STEPS = 2, F_NFLAG = 8 };
+
+struct DevTables {
+    // twiddles exp(-2 pi i t / n)
+    double2* twx64 = nullptr;
+    float2* twx32 = nullptr;
+    double2* twy64 = nullptr;
+    float2* twy32 = nullptr;
+    double* lamx = nullptr;  // [mx]
+    double* lamy = nullptr;  // [ny]
+    double* za = nullptr;    // [nz] tridiagonal sub-diagonal
+    double* zb = nullptr;    // [nz] diagonal
+    double* zc = nullptr;    // [nz] super-diagonal
+    double* inv_h = nullptr; // [nz]
+    double* inv_g = nullptr; // [nz+1], face k between cells k-1 and k (walls: 0)
+    double* h = nullptr;     // [nz]
+    double* vol = nullptr;   // [nz]
+    double* inv_vol = nullptr;
+};
+
+struct Launch {
+    int lbx = 8;       // lines per block, x passes
+    int lby = 8;       // lines per block, y passes
+    int thr_x = 256;
+    int thr_y = 256;
+    int thr_z = 256;
+};
+
+// Optional per-kernel timing: a pair of hipEvents around every launch on the
+// launch stream, summed per kernel name when the summary is read.
+struct TraceRec {
+    const char* name;
+    hipEvent_t a, b;
+};
+struct Trace {
+    bool on = false;
+    std::vector<TraceRec> recs;
+    std::vector<hipEvent_t> pool;
+    size_t next = 0;
+    hipEvent_t get();
+    void release_all();
+};
+
+struct Plan;
+class TraceScope {
+public:
+    TraceScope(const Plan& p, const char* name, hipStream_t s);
+    ~TraceScope();
+    TraceScope(const TraceScope&) = delete;
+    TraceScope& operator=(const TraceScope&) = delete;
+
+private:
+    Trace* t_;
+    hipStream_t s_;
+    size_t idx_;
+};
+
+struct Plan {
+    mutable Trace trace;
+    psv_grid grid{};
+    psv_opts opts{};
+    int nx = 0, ny = 0, nz = 0, mx = 0;
+    double dx = 0, dy = 0;
+    std::vector<double> zf, h, zcen, g;
+    Radices rad_xh{}, rad_y{};  // complex half-length x, full y
+    DevTables t;
+    Launch lp;
+    int device = 0;
+    // workspace
+    void* spec = nullptr;      // [nz][mx][ny] complex, FP64 or FP32
+    void* cp = nullptr;        // Thomas pivots scratch [nz][mx][ny] (same real type)
+    double* r_ws = nullptr;    // FP64 right-hand side [N]
+    double* partials = nullptr;
+    int n_partials = 0;
+    double* scal = nullptr;    // [S_NSCAL]
+    int* flags = nullptr;      // [F_NFLAG]
+    double* host_scal = nullptr;  // pinned mirror
+    int* host_flags = nullptr;
+    size_t ws_bytes = 0;
+    bool own_ws = true;
+    size_t ncell() const { return (size_t)nx * ny * nz; }
+    size_t nspec() const { return (size_t)mx * ny * nz; }
+};
+
+// Builds host tables and uploads them; allocates workspace when alloc_ws.
+void plan_init(Plan& p, const psv_grid& g, const psv_opts& o, bool alloc_ws);
+void plan_free(Plan& p);
+
+// ---- launchers (kernels in *.hip) ----
+struct FwdArgs {
+    int mode;
+    const double* f;
+    const double* rho;
+    const double* pprev;  // METHOD1: previous pressure; RESID: current p
+    const double* r_in;   // RESID: stored RHS
+    const double* scale;  // CONST: per-k scale or null
+    double* r_out;        // optional: store the assembled RHS
+    const double* rho0;   // device scalar
+    const double* mean;   // RESID: device scalar (mean removed from r)
+    double* partials;     // RESID: 2 per block
+    const int* done;      // skip when *done != 0 (may be null)
+};
+void launch_fwd_x(const Plan& p, bool fp32, const FwdArgs& a, hipStream_t s);
+void launch_fft_y(const Plan& p, bool fp32, bool inverse, const int* done, hipStream_t s);
+void launch_thomas(const Plan& p, bool fp32, double* mean_out, const int* done, hipStream_t s);
+void launch_inv_x(const Plan& p, bool fp32, int mode, double* out, double scale_all,
+                  const int* done, hipStream_t s);
+
+void launch_min_reduce(const Plan& p, const double* x, double* out_scalar, int* argmin_out,
+                       hipStream_t s);
+void launch_norm_finalize(const Plan& p, int nblocks, double tol, hipStream_t s);
+void launch_residual(const Plan& p, const double* r, const double* p_sol, const double* mean,
+                     hipStream_t s);
+int fwd_x_blocks(const Plan& p);
+void launch_set_scalar(double* dst, double v, hipStream_t s);
+void launch_density(const Plan& p, const double* phi, const double* rg, double rl, double* out,
+                    hipStream_t s);
+void launch_divergence(const Plan& p, const double* ux, const double* uy, const double* uz,
+                       double* out, hipStream_t s);
+void launch_adjoint_faces(const Plan& p, const double* x, const double* f, const double* rho,
+                          const double* pprev, const double* rho0, double* grad_f,
+                          double* grad_rho, double* grad_p, double* partials, hipStream_t s);
+void launch_adjoint_finalize(const Plan& p, int nblocks, double* grad_rho, int add_argmin,
+                             hipStream_t s);
+int adjoint_blocks(const Plan& p);
+void launch_scale_vol(const Plan& p, const double* x, double* out, hipStream_t s);
+void launch_vmean(const Plan& p, const double* r, double* out_scalar, hipStream_t s);
+void launch_fill(double* x, size_t n, double v, hipStream_t s);
+// volume-weighted mean from the forward pass's per-block sums of vol * r
+void launch_mean_finalize(const Plan& p, int nblocks, double* out_scalar, hipStream_t s);
+void launch_scan_inputs(const Plan& p, const double* x, int positive, int* bad, hipStream_t s);
+
+}  // namespace psv

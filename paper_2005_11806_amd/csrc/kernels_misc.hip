@@ -1,0 +1,423 @@
+// Pointwise and reduction kernels around the solve: min(rho) with its first
+// index (rho0 of Method I, Sec. 3.3.1), residual norms, the mixture density
+// (Sec. 2.2, Eq. eq_22), the discrete divergence, input scans and the
+// face terms of the adjoint of one Method-I step.
+// Reductions are two-stage (per-block partials, then one block) so that
+// their results do not depend on scheduling.
+#include "internal.hpp"
+
+namespace psv {
+namespace {
+
+constexpr int RB = 256;      // threads per reduction block
+constexpr int RMAXB = 1024;  // partial blocks of a reduction
+
+__global__ void __launch_bounds__(RB) k_min_partial(const double* __restrict__ x, size_t n,
+                                                    double* pv, int* pi) {
+    __shared__ double sv[RB];
+    __shared__ int si[RB];
+    double best = __builtin_inf();
+    int bi = 0x7fffffff;
+    for (size_t c = (size_t)blockIdx.x * RB + threadIdx.x; c < n; c += (size_t)gridDim.x * RB) {
+        const double v = x[c];
+        if (v < best) { best = v; bi = (int)c; }
+    }
+    sv[threadIdx.x] = best;
+    si[threadIdx.x] = bi;
+    __syncthreads();
+    for (int o = RB / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) {
+            const double v = sv[threadIdx.x + o];
+            const int i = si[threadIdx.x + o];
+            if (v < sv[threadIdx.x] || (v == sv[threadIdx.x] && i < si[threadIdx.x])) {
+                sv[threadIdx.x] = v;
+                si[threadIdx.x] = i;
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        pv[blockIdx.x] = sv[0];
+        pi[blockIdx.x] = si[0];
+    }
+}
+
+__global__ void __launch_bounds__(RB) k_min_final(const double* pv, const int* pi, int nb,
+                                                  double* out, int* argmin) {
+    __shared__ double sv[RB];
+    __shared__ int si[RB];
+    double best = __builtin_inf();
+    int bi = 0x7fffffff;
+    for (int b = threadIdx.x; b < nb; b += RB) {
+        if (pv[b] < best || (pv[b] == best && pi[b] < bi)) { best = pv[b]; bi = pi[b]; }
+    }
+    sv[threadIdx.x] = best;
+    si[threadIdx.x] = bi;
+    __syncthreads();
+    for (int o = RB / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) {
+            const double v = sv[threadIdx.x + o];
+            const int i = si[threadIdx.x + o];
+            if (v < sv[threadIdx.x] || (v == sv[threadIdx.x] && i < si[threadIdx.x])) {
+                sv[threadIdx.x] = v;
+                si[threadIdx.x] = i;
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        *out = sv[0];
+        if (argmin) *argmin = si[0];
+    }
+}
+
+// Sum of `per` interleaved partial sums over nb blocks.
+__global__ void __launch_bounds__(RB) k_sum_partials(const double* partials, int nb, int per,
+                                                     double* out) {
+    __shared__ double sh[16];
+    for (int q = 0; q < per; ++q) {
+        double v = 0.0;
+        for (int b = threadIdx.x; b < nb; b += RB) v += partials[(size_t)per * b + q];
+        const double s = block_sum(v, sh);
+        if (threadIdx.x == 0) out[q] = s;
+        __syncthreads();
+    }
+}
+
+// relres = sqrt(sum res^2 / sum r^2); sets flags[F_DONE] when <= tol.
+__global__ void k_relres_final(double* scal, int* flags, double tol) {
+    if (threadIdx.x == 0) {
+        const double r2 = scal[S_R2];
+        const double rr = r2 > 0.0 ? sqrt(scal[S_RES2] / r2) : 0.0;
+        scal[S_RELRES] = rr;
+        if (tol > 0.0 && rr <= tol) flags[F_DONE] = 1;
+    }
+}
+
+__global__ void k_set_scalar(double* dst, double v) {
+    if (threadIdx.x == 0) *dst = v;
+}
+
+struct Geo {
+    int nx, ny, nz;
+    double inv_dx, inv_dy;
+    const double* inv_h;
+    const double* inv_g;
+    const double* vol;
+};
+
+__device__ __forceinline__ void cell_coords(size_t c, const Geo& g, int& i, int& j, int& k) {
+    i = (int)(c % g.nx);
+    const size_t q = c / g.nx;
+    j = (int)(q % g.ny);
+    k = (int)(q / g.ny);
+}
+
+// res = r - mean - L p ; partial sums of res^2 and (r - mean)^2
+__global__ void __launch_bounds__(RB) k_residual(Geo g, const double* __restrict__ r,
+                                                 const double* __restrict__ p,
+                                                 const double* mean_p, double* partials) {
+    __shared__ double sh[16];
+    const size_t n = (size_t)g.nx * g.ny * g.nz;
+    const size_t plane = (size_t)g.nx * g.ny;
+    const double mean = *mean_p;
+    double s1 = 0.0, s2 = 0.0;
+    for (size_t c = (size_t)blockIdx.x * RB + threadIdx.x; c < n; c += (size_t)gridDim.x * RB) {
+        int i, j, k;
+        cell_coords(c, g, i, j, k);
+        const size_t row = c - i;
+        const double pc = p[c];
+        const double pe = p[row + (i + 1 == g.nx ? 0 : i + 1)];
+        const double pw = p[row + (i == 0 ? g.nx - 1 : i - 1)];
+        const double pn = p[c - (size_t)j * g.nx + (size_t)(j + 1 == g.ny ? 0 : j + 1) * g.nx];
+        const double ps = p[c - (size_t)j * g.nx + (size_t)(j == 0 ? g.ny - 1 : j - 1) * g.nx];
+        double lp = ((pe - pc) - (pc - pw)) * (g.inv_dx * g.inv_dx) +
+                    ((pn - pc) - (pc - ps)) * (g.inv_dy * g.inv_dy);
+        const double ft = (k + 1 < g.nz) ? (p[c + plane] - pc) * g.inv_g[k + 1] : 0.0;
+        const double fb = (k > 0) ? (pc - p[c - plane]) * g.inv_g[k] : 0.0;
+        lp += (ft - fb) * g.inv_h[k];
+        const double rp = r[c] - mean;
+        const double res = rp - lp;
+        s1 += res * res;
+        s2 += rp * rp;
+    }
+    const double a = block_sum(s1, sh);
+    __syncthreads();
+    const double b = block_sum(s2, sh);
+    if (threadIdx.x == 0) {
+        partials[2 * blockIdx.x] = a;
+        partials[2 * blockIdx.x + 1] = b;
+    }
+}
+
+__global__ void k_density(size_t n, const double* __restrict__ phi, const double* __restrict__ rg,
+                          double rl, double* __restrict__ out) {
+    for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < n;
+         c += (size_t)gridDim.x * blockDim.x) {
+        const double f = phi[c];
+        out[c] = rg[c] * f + rl * (1.0 - f);
+    }
+}
+
+__global__ void k_divergence(Geo g, const double* __restrict__ ux, const double* __restrict__ uy,
+                             const double* __restrict__ uz, double* __restrict__ out) {
+    const size_t n = (size_t)g.nx * g.ny * g.nz;
+    const size_t plane = (size_t)g.nx * g.ny;
+    for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < n;
+         c += (size_t)gridDim.x * blockDim.x) {
+        int i, j, k;
+        cell_coords(c, g, i, j, k);
+        const size_t row = c - i;
+        const double dx = ux[c] - ux[row + (i == 0 ? g.nx - 1 : i - 1)];
+        const double dy = uy[c] - uy[c - (size_t)j * g.nx + (size_t)(j == 0 ? g.ny - 1 : j - 1) * g.nx];
+        // uz is [nz+1][ny][nx]: the bottom face of cell c has index c, the top c + plane
+        const double dz = uz[c + plane] - uz[c];
+        out[c] = dx * g.inv_dx + dy * g.inv_dy + dz * g.inv_h[k];
+    }
+}
+
+// Adjoint face terms of one Method-I step for loss = sum(w p). The solve S is
+// self-adjoint in the volume-weighted inner product, so S^T w = V S(V^-1 w);
+// the kernel receives x = S(V^-1 w) and forms lam = V x. With beta_f =
+// 1 - rho0/rho_f and rho_f = (rho_L + rho_R)/2:
+//   (D^T lam)_f = lam_L/h_L - lam_R/h_R, gface = (D^T lam)_f (G p_prev)_f,
+//   grad_f[c]    = rho0 lam_c,
+//   grad_rho[c]  = sum over the 6 faces of c of gface rho0 / (2 rho_f^2),
+//   grad_p[c]    = (G^T (beta D^T lam))_c,
+//   partials     = sum lam f - sum over faces (each once) of gface / rho_f.
+struct AdjArgs {
+    const double* x;  // S(V^-1 w)
+    const double* f;
+    const double* rho;
+    const double* pp;
+    const double* rho0p;
+    double* grad_f;
+    double* grad_rho;
+    double* grad_p;
+    double* partials;
+};
+
+__global__ void __launch_bounds__(RB) k_adjoint_faces(Geo g, AdjArgs a) {
+    __shared__ double sh[16];
+    const size_t n = (size_t)g.nx * g.ny * g.nz;
+    const size_t plane = (size_t)g.nx * g.ny;
+    const double rho0 = *a.rho0p;
+    double acc = 0.0;
+    for (size_t c = (size_t)blockIdx.x * RB + threadIdx.x; c < n; c += (size_t)gridDim.x * RB) {
+        int i, j, k;
+        cell_coords(c, g, i, j, k);
+        const size_t row = c - i;
+        const double lc = g.vol[k] * a.x[c], rc = a.rho[c], pc = a.pp[c];
+        const double ihc = g.inv_h[k];
+        double gr = 0.0, gp = 0.0;
+        // neighbour offsets: east, west, north, south, top, bottom
+        size_t nb[6];
+        bool has[6] = {true, true, true, true, k + 1 < g.nz, k > 0};
+        nb[0] = row + (i + 1 == g.nx ? 0 : i + 1);
+        nb[1] = row + (i == 0 ? g.nx - 1 : i - 1);
+        nb[2] = c - (size_t)j * g.nx + (size_t)(j + 1 == g.ny ? 0 : j + 1) * g.nx;
+        nb[3] = c - (size_t)j * g.nx + (size_t)(j == 0 ? g.ny - 1 : j - 1) * g.nx;
+        nb[4] = has[4] ? c + plane : c;
+        nb[5] = has[5] ? c - plane : c;
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            if (!has[q]) continue;
+            const size_t o = nb[q];
+            const int ko = (q == 4) ? k + 1 : (q == 5 ? k - 1 : k);
+            const double lo = g.vol[ko] * a.x[o], ro = a.rho[o], po = a.pp[o];
+            // plus faces (q even): c is the left cell; minus faces: c is the right cell
+            const bool plus = (q & 1) == 0;
+            double ihc_o, inv_d;
+            if (q < 2) { ihc_o = g.inv_dx; inv_d = g.inv_dx; }
+            else if (q < 4) { ihc_o = g.inv_dy; inv_d = g.inv_dy; }
+            else { ihc_o = g.inv_h[q == 4 ? k + 1 : k - 1]; inv_d = g.inv_g[q == 4 ? k + 1 : k]; }
+            const double ihl = (q < 4) ? ihc_o : ihc;  // own width in this direction
+            const double dt = plus ? (lc * ihl - lo * ihc_o) : (lo * ihc_o - lc * ihl);
+            const double gpf = plus ? (po - pc) * inv_d : (pc - po) * inv_d;
+            const double rf = 0.5 * (rc + ro);
+            const double gf = dt * gpf;
+            gr += 0.5 * gf * rho0 / (rf * rf);
+            const double bdt = (1.0 - rho0 / rf) * dt;
+            gp += plus ? -bdt * inv_d : bdt * inv_d;
+            if (plus) acc -= gf / rf;
+        }
+        acc += lc * (a.f ? a.f[c] : 0.0);
+        if (a.grad_f) a.grad_f[c] = rho0 * lc;
+        if (a.grad_rho) a.grad_rho[c] = gr;
+        if (a.grad_p) a.grad_p[c] = gp;
+    }
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) a.partials[blockIdx.x] = s;
+}
+
+__global__ void k_scale_vol(Geo g, const double* __restrict__ x, double* __restrict__ out) {
+    const size_t n = (size_t)g.nx * g.ny * g.nz;
+    const size_t plane = (size_t)g.nx * g.ny;
+    for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < n;
+         c += (size_t)gridDim.x * blockDim.x)
+        out[c] = g.vol[c / plane] * x[c];
+}
+
+// partial sums of vol[k] r[c] (volume-weighted integral)
+__global__ void __launch_bounds__(RB) k_vsum(Geo g, const double* __restrict__ r, double* partials) {
+    __shared__ double sh[16];
+    const size_t n = (size_t)g.nx * g.ny * g.nz;
+    const size_t plane = (size_t)g.nx * g.ny;
+    double acc = 0.0;
+    for (size_t c = (size_t)blockIdx.x * RB + threadIdx.x; c < n; c += (size_t)gridDim.x * RB)
+        acc += g.vol[c / plane] * r[c];
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+__global__ void k_div_scalar(double* x, double d) {
+    if (threadIdx.x == 0) *x = *x / d;
+}
+
+__global__ void k_fill(size_t n, double* __restrict__ x, double v) {
+    for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < n;
+         c += (size_t)gridDim.x * blockDim.x)
+        x[c] = v;
+}
+
+__global__ void k_adjoint_argmin(double* grad_rho, const double* scal, const int* flags) {
+    if (threadIdx.x == 0) grad_rho[flags[F_ARGMIN]] += scal[S_GRAD_RHO0];
+}
+
+__global__ void k_scan(size_t n, const double* __restrict__ x, int positive, int* bad) {
+    int b = 0;
+    for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < n;
+         c += (size_t)gridDim.x * blockDim.x) {
+        const double v = x[c];
+        if (!isfinite(v)) b |= 1;
+        else if (positive && !(v > 0.0)) b |= 2;
+    }
+    if (b) atomicOr(bad, b);
+}
+
+Geo make_geo(const Plan& p) {
+    Geo g;
+    g.nx = p.nx;
+    g.ny = p.ny;
+    g.nz = p.nz;
+    g.inv_dx = 1.0 / p.dx;
+    g.inv_dy = 1.0 / p.dy;
+    g.inv_h = p.t.inv_h;
+    g.inv_g = p.t.inv_g;
+    g.vol = p.t.vol;
+    return g;
+}
+
+int grid_blocks(size_t n, int thr) {
+    size_t b = (n + thr - 1) / thr;
+    if (b > (size_t)RMAXB) b = RMAXB;
+    return (int)(b < 1 ? 1 : b);
+}
+
+}  // namespace
+
+int adjoint_blocks(const Plan& p) { return grid_blocks(p.ncell(), RB); }
+
+void launch_min_reduce(const Plan& p, const double* x, double* out_scalar, int* argmin_out,
+                       hipStream_t s) {
+    const int nb = grid_blocks(p.ncell(), RB);
+    double* pv = p.partials;
+    int* pi = reinterpret_cast<int*>(p.partials + RMAXB);
+    TraceScope ts(p, "min_rho", s);
+    hipLaunchKernelGGL(k_min_partial, dim3(nb), dim3(RB), 0, s, x, p.ncell(), pv, pi);
+    hipLaunchKernelGGL(k_min_final, dim3(1), dim3(RB), 0, s, pv, pi, nb, out_scalar, argmin_out);
+    PSV_HIP(hipGetLastError());
+}
+
+void launch_norm_finalize(const Plan& p, int nblocks, double tol, hipStream_t s) {
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(RB), 0, s, p.partials, nblocks, 2,
+                       p.scal + S_RES2);
+    hipLaunchKernelGGL(k_relres_final, dim3(1), dim3(64), 0, s, p.scal, p.flags, tol);
+    PSV_HIP(hipGetLastError());
+}
+
+void launch_residual(const Plan& p, const double* r, const double* p_sol, const double* mean,
+                     hipStream_t s) {
+    const int nb = grid_blocks(p.ncell(), RB);
+    {
+        TraceScope ts(p, "residual_fp64", s);
+        hipLaunchKernelGGL(k_residual, dim3(nb), dim3(RB), 0, s, make_geo(p), r, p_sol, mean,
+                           p.partials);
+    }
+    launch_norm_finalize(p, nb, 0.0, s);
+}
+
+void launch_set_scalar(double* dst, double v, hipStream_t s) {
+    hipLaunchKernelGGL(k_set_scalar, dim3(1), dim3(64), 0, s, dst, v);
+    PSV_HIP(hipGetLastError());
+}
+
+void launch_density(const Plan& p, const double* phi, const double* rg, double rl, double* out,
+                    hipStream_t s) {
+    const int nb = grid_blocks(p.ncell(), RB) * 4;
+    hipLaunchKernelGGL(k_density, dim3(nb), dim3(RB), 0, s, p.ncell(), phi, rg, rl, out);
+    PSV_HIP(hipGetLastError());
+}
+
+void launch_divergence(const Plan& p, const double* ux, const double* uy, const double* uz,
+                       double* out, hipStream_t s) {
+    const int nb = grid_blocks(p.ncell(), RB) * 4;
+    hipLaunchKernelGGL(k_divergence, dim3(nb), dim3(RB), 0, s, make_geo(p), ux, uy, uz, out);
+    PSV_HIP(hipGetLastError());
+}
+
+void launch_adjoint_faces(const Plan& p, const double* x, const double* f, const double* rho,
+                          const double* pprev, const double* rho0, double* grad_f,
+                          double* grad_rho, double* grad_p, double* partials, hipStream_t s) {
+    AdjArgs a{x, f, rho, pprev, rho0, grad_f, grad_rho, grad_p, partials};
+    hipLaunchKernelGGL(k_adjoint_faces, dim3(adjoint_blocks(p)), dim3(RB), 0, s, make_geo(p), a);
+    PSV_HIP(hipGetLastError());
+}
+
+void launch_adjoint_finalize(const Plan& p, int nblocks, double* grad_rho, int add_argmin,
+                             hipStream_t s) {
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(RB), 0, s, p.partials, nblocks, 1,
+                       p.scal + S_GRAD_RHO0);
+    if (add_argmin && grad_rho)
+        hipLaunchKernelGGL(k_adjoint_argmin, dim3(1), dim3(64), 0, s, grad_rho, p.scal, p.flags);
+    PSV_HIP(hipGetLastError());
+}
+
+void launch_scale_vol(const Plan& p, const double* x, double* out, hipStream_t s) {
+    const int nb = grid_blocks(p.ncell(), RB) * 4;
+    hipLaunchKernelGGL(k_scale_vol, dim3(nb), dim3(RB), 0, s, make_geo(p), x, out);
+    PSV_HIP(hipGetLastError());
+}
+
+void launch_vmean(const Plan& p, const double* r, double* out_scalar, hipStream_t s) {
+    const int nb = grid_blocks(p.ncell(), RB);
+    hipLaunchKernelGGL(k_vsum, dim3(nb), dim3(RB), 0, s, make_geo(p), r, p.partials);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(RB), 0, s, p.partials, nb, 1, out_scalar);
+    double total = 0.0;
+    for (double h : p.h) total += h;
+    hipLaunchKernelGGL(k_div_scalar, dim3(1), dim3(64), 0, s, out_scalar, p.dx * p.dy * total * p.nx * p.ny);
+    PSV_HIP(hipGetLastError());
+}
+
+void launch_mean_finalize(const Plan& p, int nblocks, double* out_scalar, hipStream_t s) {
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(RB), 0, s, p.partials, nblocks, 1, out_scalar);
+    double total = 0.0;
+    for (double h : p.h) total += h;
+    hipLaunchKernelGGL(k_div_scalar, dim3(1), dim3(64), 0, s, out_scalar, p.dx * p.dy * total * p.nx * p.ny);
+    PSV_HIP(hipGetLastError());
+}
+
+void launch_fill(double* x, size_t n, double v, hipStream_t s) {
+    size_t b = (n + RB - 1) / RB;
+    if (b > 4096) b = 4096;
+    hipLaunchKernelGGL(k_fill, dim3((int)(b < 1 ? 1 : b)), dim3(RB), 0, s, n, x, v);
+    PSV_HIP(hipGetLastError());
+}
+
+void launch_scan_inputs(const Plan& p, const double* x, int positive, int* bad, hipStream_t s) {
+    const int nb = grid_blocks(p.ncell(), RB);
+    hipLaunchKernelGGL(k_scan, dim3(nb), dim3(RB), 0, s, p.ncell(), x, positive, bad);
+    PSV_HIP(hipGetLastError());
+}
+
+}  // namespace psv

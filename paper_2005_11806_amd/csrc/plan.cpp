@@ -1,0 +1,247 @@
+// Plan construction: grid validation, FP64 host tables (z geometry and the
+// wall-normal tridiagonal coefficients, eigenvalues of the periodic second
+// differences, FFT twiddles) and the device workspace.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <sstream>
+
+#include "internal.hpp"
+
+namespace psv {
+
+[[noreturn]] void fail(psv_status s, const std::string& msg) { throw Error{s, msg}; }
+
+void hip_check(hipError_t e, const char* what) {
+    if (e != hipSuccess) {
+        std::ostringstream os;
+        os << what << ": " << hipGetErrorString(e);
+        fail(e == hipErrorOutOfMemory ? PSV_ERR_OOM : PSV_ERR_HIP, os.str());
+    }
+}
+
+static bool is_23_smooth(int n) {
+    if (n <= 0) return false;
+    while (n % 2 == 0) n /= 2;
+    while (n % 3 == 0) n /= 3;
+    return n == 1;
+}
+
+Radices make_radices(int n) {
+    Radices r{};
+    r.n = n;
+    int a = 0, b = 0, m = n;
+    while (m % 2 == 0) { m /= 2; ++a; }
+    while (m % 3 == 0) { m /= 3; ++b; }
+    while (a >= 3) { r.r[r.count++] = 8; a -= 3; }
+    if (a == 2) r.r[r.count++] = 4;
+    if (a == 1) r.r[r.count++] = 2;
+    while (b-- > 0) r.r[r.count++] = 3;
+    return r;
+}
+
+// Host-side checks of a grid; no device access.
+void validate_grid(const psv_grid* g) {
+    if (!g) fail(PSV_ERR_INVALID_ARG, "grid is NULL");
+    if (g->bc_z != PSV_BC_WALL_NEUMANN) fail(PSV_ERR_INVALID_ARG, "unknown z boundary condition");
+    if (g->nz < 2) fail(PSV_ERR_INVALID_ARG, "nz must be >= 2");
+    if (g->nz > 2048) fail(PSV_ERR_UNSUPPORTED_SIZE, "nz must be <= 2048");
+    for (int n : {g->nx, g->ny}) {
+        if (n < 4 || n > 1024 || (n & 1) || !is_23_smooth(n))
+            fail(PSV_ERR_UNSUPPORTED_SIZE, "nx and ny must be even, of the form 2^a 3^b, in [4, 1024]");
+    }
+    if (!(g->lx > 0) || !(g->ly > 0) || !(g->lz > 0) || !std::isfinite(g->lx) ||
+        !std::isfinite(g->ly) || !std::isfinite(g->lz))
+        fail(PSV_ERR_INVALID_ARG, "domain lengths must be positive and finite");
+    const double ncell = (double)g->nx * g->ny * g->nz;
+    if (ncell >= 2147483647.0) fail(PSV_ERR_UNSUPPORTED_SIZE, "nx*ny*nz must be < 2^31");
+    if (g->zf) {
+        if (g->zf[0] != 0.0) fail(PSV_ERR_INVALID_ARG, "zf[0] must be 0");
+        if (std::fabs(g->zf[g->nz] - g->lz) > 1e-12 * g->lz) fail(PSV_ERR_INVALID_ARG, "zf[nz] must equal lz");
+        for (int k = 0; k < g->nz; ++k) {
+            if (!(g->zf[k + 1] > g->zf[k]) || !std::isfinite(g->zf[k + 1]))
+                fail(PSV_ERR_INVALID_ARG, "zf must be finite and strictly increasing");
+        }
+    }
+}
+
+void validate_opts(const psv_opts* o) {
+    if (!o) return;
+    if (o->precision != PSV_FP64 && o->precision != PSV_MIXED) fail(PSV_ERR_INVALID_ARG, "bad precision");
+    if (o->method != PSV_CONST && o->method != PSV_SPLIT_RHO0) fail(PSV_ERR_INVALID_ARG, "bad method");
+    if (o->max_refine > 64) fail(PSV_ERR_INVALID_ARG, "max_refine must be <= 64");
+    if (!(o->tol >= 0.0) && !(o->tol < 0.0)) fail(PSV_ERR_INVALID_ARG, "tol is NaN");
+    if (o->check_inputs != 0 && o->check_inputs != 1) fail(PSV_ERR_INVALID_ARG, "check_inputs must be 0 or 1");
+    if (o->autotune < 0 || o->autotune > 2) fail(PSV_ERR_INVALID_ARG, "autotune must be 0..2");
+}
+
+void default_opts(psv_opts* o) {
+    std::memset(o, 0, sizeof(*o));
+    o->precision = PSV_FP64;
+    o->method = PSV_SPLIT_RHO0;
+    o->tol = 1e-10;
+    o->max_refine = 4;
+    o->check_inputs = 0;
+    o->autotune = 0;
+}
+
+// exp(-2 pi i t / n), t = 0..n-1, from the angle reduced to the first octant
+// in extended precision.
+static void twiddles(int n, std::vector<double>& re, std::vector<double>& im) {
+    re.resize(n);
+    im.resize(n);
+    const long double two_pi = 6.283185307179586476925286766559005768L;
+    for (int t = 0; t < n; ++t) {
+        const long double a = two_pi * (long double)t / (long double)n;
+        re[t] = (double)cosl(a);
+        im[t] = (double)-sinl(a);
+    }
+    // exact values on the axes
+    for (int t = 0; t < n; ++t) {
+        if ((4 * t) % n == 0) {
+            const int q = (4 * t) / n;
+            re[t] = (q == 0) ? 1.0 : (q == 2 ? -1.0 : 0.0);
+            im[t] = (q == 1) ? -1.0 : (q == 3 ? 1.0 : 0.0);
+        }
+    }
+}
+
+template <typename T>
+static T* upload(const std::vector<T>& v) {
+    T* d = nullptr;
+    PSV_HIP(hipMalloc(&d, v.size() * sizeof(T)));
+    PSV_HIP(hipMemcpy(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    return d;
+}
+
+static int pick_lines(int ny, size_t bytes_per_line, size_t budget, int cap) {
+    int lb = 1;
+    while (lb * 2 <= cap && ny % (lb * 2) == 0 && (size_t)(lb * 2) * bytes_per_line <= budget) lb *= 2;
+    return lb;
+}
+
+void plan_init(Plan& p, const psv_grid& g, const psv_opts& o, bool alloc_ws) {
+    p.grid = g;
+    p.opts = o;
+    if (p.opts.tol <= 0.0) p.opts.tol = 1e-10;
+    if (p.opts.max_refine <= 0) p.opts.max_refine = 4;
+    p.nx = g.nx;
+    p.ny = g.ny;
+    p.nz = g.nz;
+    p.mx = g.nx / 2 + 1;
+    p.dx = g.lx / g.nx;
+    p.dy = g.ly / g.ny;
+    const int nz = g.nz;
+    p.zf.resize(nz + 1);
+    for (int k = 0; k <= nz; ++k) p.zf[k] = g.zf ? g.zf[k] : g.lz * (double)k / nz;
+    p.zf[0] = 0.0;
+    p.zf[nz] = g.lz;
+    p.grid.zf = nullptr;  // the caller's array is not retained
+    p.h.resize(nz);
+    p.zcen.resize(nz);
+    p.g.assign(nz + 1, 0.0);
+    for (int k = 0; k < nz; ++k) {
+        p.h[k] = p.zf[k + 1] - p.zf[k];
+        p.zcen[k] = 0.5 * (p.zf[k] + p.zf[k + 1]);
+    }
+    for (int k = 1; k < nz; ++k) p.g[k] = p.zcen[k] - p.zcen[k - 1];
+    // wall-normal operator: a_k x_{k-1} + b_k x_k + c_k x_{k+1}
+    std::vector<double> a(nz, 0.0), b(nz, 0.0), c(nz, 0.0), inv_h(nz), inv_g(nz + 1, 0.0), vol(nz),
+        inv_vol(nz);
+    for (int k = 0; k < nz; ++k) {
+        if (k > 0) a[k] = 1.0 / (p.h[k] * p.g[k]);
+        if (k + 1 < nz) c[k] = 1.0 / (p.h[k] * p.g[k + 1]);
+        b[k] = -(a[k] + c[k]);
+        inv_h[k] = 1.0 / p.h[k];
+        vol[k] = p.dx * p.dy * p.h[k];
+        inv_vol[k] = 1.0 / vol[k];
+    }
+    for (int k = 1; k < nz; ++k) inv_g[k] = 1.0 / p.g[k];
+    // eigenvalues of the periodic second differences, -4 sin^2(pi m / n) / d^2
+    std::vector<double> lamx(p.mx), lamy(p.ny);
+    const long double pi_l = 3.141592653589793238462643383279502884L;
+    for (int m = 0; m < p.mx; ++m) {
+        const long double s = sinl(pi_l * m / p.nx);
+        lamx[m] = (double)(-4.0L * s * s / ((long double)p.dx * p.dx));
+    }
+    for (int n = 0; n < p.ny; ++n) {
+        const long double s = sinl(pi_l * n / p.ny);
+        lamy[n] = (double)(-4.0L * s * s / ((long double)p.dy * p.dy));
+    }
+    std::vector<double> re, im;
+    std::vector<double2> tx64(p.nx), ty64(p.ny);
+    std::vector<float2> tx32(p.nx), ty32(p.ny);
+    twiddles(p.nx, re, im);
+    for (int t = 0; t < p.nx; ++t) {
+        tx64[t] = double2{re[t], im[t]};
+        tx32[t] = float2{(float)re[t], (float)im[t]};
+    }
+    twiddles(p.ny, re, im);
+    for (int t = 0; t < p.ny; ++t) {
+        ty64[t] = double2{re[t], im[t]};
+        ty32[t] = float2{(float)re[t], (float)im[t]};
+    }
+    p.rad_xh = make_radices(p.nx / 2);
+    p.rad_y = make_radices(p.ny);
+    PSV_HIP(hipGetDevice(&p.device));
+    // launch shapes: lines per block bounded by the LDS a block may take (FP64
+    // worst case), leaving 2 KiB for static shared arrays
+    int lds_max = 0;
+    PSV_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, p.device));
+    const size_t budget = (size_t)std::min(lds_max, 64 * 1024) - 2048;
+    p.lp.lbx = pick_lines(p.ny, (size_t)(p.nx + 1) * sizeof(double2), budget, 16);
+    p.lp.lby = pick_lines(1 << 20, (size_t)2 * p.ny * sizeof(double2), budget, 16);
+    if ((size_t)p.lp.lbx * (p.nx + 1) * sizeof(double2) > budget ||
+        (size_t)p.lp.lby * 2 * p.ny * sizeof(double2) > budget)
+        fail(PSV_ERR_UNSUPPORTED_SIZE, "line length exceeds the LDS budget");
+
+    p.t.twx64 = upload(tx64);
+    p.t.twx32 = upload(tx32);
+    p.t.twy64 = upload(ty64);
+    p.t.twy32 = upload(ty32);
+    p.t.lamx = upload(lamx);
+    p.t.lamy = upload(lamy);
+    p.t.za = upload(a);
+    p.t.zb = upload(b);
+    p.t.zc = upload(c);
+    p.t.inv_h = upload(inv_h);
+    p.t.inv_g = upload(inv_g);
+    p.t.h = upload(p.h);
+    p.t.vol = upload(vol);
+    p.t.inv_vol = upload(inv_vol);
+    // per-block partial sums: 2 per forward-x block, or the reductions' 1.5 * 1024
+    p.n_partials = std::max(8192, 2 * (p.ny / p.lp.lbx) * p.nz + 64);
+    PSV_HIP(hipMalloc(&p.partials, p.n_partials * sizeof(double)));
+    PSV_HIP(hipMalloc(&p.scal, S_NSCAL * sizeof(double)));
+    PSV_HIP(hipMalloc(&p.flags, F_NFLAG * sizeof(int)));
+    PSV_HIP(hipMemset(p.scal, 0, S_NSCAL * sizeof(double)));
+    PSV_HIP(hipMemset(p.flags, 0, F_NFLAG * sizeof(int)));
+    PSV_HIP(hipHostMalloc(&p.host_scal, S_NSCAL * sizeof(double)));
+    PSV_HIP(hipHostMalloc(&p.host_flags, F_NFLAG * sizeof(int)));
+    const size_t nspec = p.nspec(), ncell = p.ncell();
+    p.ws_bytes = nspec * sizeof(double2) + nspec * sizeof(double) + 2 * ncell * sizeof(double);
+    if (alloc_ws) {
+        PSV_HIP(hipMalloc(&p.spec, nspec * sizeof(double2)));
+        PSV_HIP(hipMalloc(&p.cp, nspec * sizeof(double)));
+        PSV_HIP(hipMalloc(&p.r_ws, 2 * ncell * sizeof(double)));
+        p.own_ws = true;
+    }
+}
+
+void plan_free(Plan& p) {
+    void* ptrs[] = {p.t.twx64, p.t.twx32, p.t.twy64, p.t.twy32, p.t.lamx, p.t.lamy, p.t.za,
+                    p.t.zb, p.t.zc, p.t.inv_h, p.t.inv_g, p.t.h, p.t.vol, p.t.inv_vol,
+                    p.partials, p.scal, p.flags};
+    for (void* q : ptrs)
+        if (q) (void)hipFree(q);
+    if (p.own_ws) {
+        if (p.spec) (void)hipFree(p.spec);
+        if (p.cp) (void)hipFree(p.cp);
+        if (p.r_ws) (void)hipFree(p.r_ws);
+    }
+    if (p.host_scal) (void)hipHostFree(p.host_scal);
+    if (p.host_flags) (void)hipHostFree(p.host_flags);
+    p = Plan{};
+}
+
+}  // namespace psv

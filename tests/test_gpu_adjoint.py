@@ -1,0 +1,105 @@
+"""GPU adjoint of one Method-I step (loss = sum(w p)) against the oracle's
+adjoint, central finite differences of the GPU forward solve, and the
+torch.autograd wrapper."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import workloads as W
+from tests.gpu_util import dev, host, oracle_inputs, rel_max_err, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _case(shape, stretched=True, seed=11, spheres=4):
+    nx, ny, nz = shape
+    spec = W.GridSpec(nx, ny, nz, 1.0, 1.0, 1.2, W.tanh_faces(nz, 1.2, 1.5) if stretched else None)
+    case = W.two_phase_case("adj", spec, 4, seed, n_spheres=spheres, with_w=True)
+    g, f, rho, pp = oracle_inputs(case)
+    return spec, g, f, rho, pp, case.w
+
+
+@pytest.mark.parametrize("shape,prec,tol", [((16, 12, 10), "fp64", 1e-10), ((32, 48, 17), "fp64", 1e-10),
+                                            ((24, 24, 20), "mixed", 1e-7)])
+def test_adjoint_matches_oracle_explicit_rho0(gpu, shape, prec, tol):
+    spec, g, f, rho, pp, w = _case(shape)
+    rho0 = float(rho.min()) * 0.9
+    say(f"adjoint {shape} {prec}")
+    plan = gpu.Plan(gpu.Grid.from_spec(spec), precision=prec)
+    gr = plan.adjoint(dev(w), f=dev(f), rho=dev(rho), p_prev=dev(pp), rho0=rho0,
+                      grad_p_prev=True, grad_rho0=True)
+    ref = O.adjoint_step(w, f, rho, rho0, pp, g)
+    e = {k: rel_max_err(host(gr[k]), getattr(ref, a)) for k, a in
+         (("f", "grad_f"), ("rho", "grad_rho"), ("p_prev", "grad_p_prev"))}
+    e["rho0"] = abs(gr["rho0"] - ref.grad_rho0) / abs(ref.grad_rho0)
+    say(f"  {e}")
+    assert all(v <= tol for v in e.values()), e
+
+
+def test_adjoint_auto_rho0_routes_to_argmin(gpu):
+    spec, g, f, rho, pp, w = _case((16, 18, 12), seed=12)
+    plan = gpu.Plan(gpu.Grid.from_spec(spec))
+    gr = plan.adjoint(dev(w), f=dev(f), rho=dev(rho), p_prev=dev(pp), rho0=None, grad_rho0=True)
+    rho0 = float(rho.min())
+    ref = O.adjoint_step(w, f, rho, rho0, pp, g)
+    total = ref.grad_rho.copy().ravel()
+    total[int(np.argmin(rho.ravel()))] += ref.grad_rho0
+    assert rel_max_err(host(gr["rho"]).ravel(), total) <= 1e-10
+    assert abs(gr["rho0"] - ref.grad_rho0) <= 1e-10 * abs(ref.grad_rho0)
+
+
+def test_adjoint_central_differences_of_gpu_forward(gpu):
+    """<grad, v> against (L(x + h v) - L(x - h v)) / 2h with the GPU forward
+    solve, for f (exact, linear) and rho (relative perturbation)."""
+    spec, g, f, rho, pp, w = _case((16, 16, 12), seed=13)
+    plan = gpu.Plan(gpu.Grid.from_spec(spec))
+    rho0 = 0.5 * float(rho.min())
+    F, R, P, Wd = dev(f), dev(rho), dev(pp), dev(w)
+    loss = lambda ff, rr: float((Wd * plan.solve(ff, rho=rr, p_prev=P, rho0=rho0)).sum())  # noqa
+    gr = plan.adjoint(Wd, f=F, rho=R, p_prev=P, rho0=rho0)
+    dirs = W.fd_directions(4, 4, f.shape)
+    for d in range(4):
+        v = dev(dirs[d])
+        h = 1e-3
+        fd_f = (loss(F + h * v, R) - loss(F - h * v, R)) / (2 * h)
+        assert np.isclose(fd_f, float((gr["f"] * v).sum()), rtol=1e-8)
+        h = 1e-5
+        vr = R * v
+        fd_r = (loss(F, R + h * vr) - loss(F, R - h * vr)) / (2 * h)
+        an_r = float((gr["rho"] * vr).sum())
+        say(f"  dir {d}: fd_rho {fd_r:.10e} adjoint {an_r:.10e}")
+        assert np.isclose(fd_r, an_r, rtol=1e-6)
+
+
+def test_autograd_function(gpu):
+    from paper_2005_11806_amd import pressure_solve
+    spec, g, f, rho, pp, w = _case((12, 12, 8), seed=14)
+    plan = gpu.Plan(gpu.Grid.from_spec(spec))
+    F = dev(f).requires_grad_(True)
+    R = dev(rho).requires_grad_(True)
+    P = dev(pp).requires_grad_(True)
+    p = pressure_solve(F, R, P, plan)
+    (p * dev(w)).sum().backward()
+    ref = O.adjoint_step(w, f, rho, float(rho.min()), pp, g)
+    total = ref.grad_rho.copy().ravel()
+    total[int(np.argmin(rho.ravel()))] += ref.grad_rho0
+    assert rel_max_err(host(F.grad), ref.grad_f) <= 1e-10
+    assert rel_max_err(host(R.grad).ravel(), total) <= 1e-9
+    assert rel_max_err(host(P.grad), ref.grad_p_prev) <= 1e-10
+    # the forward value equals a plain solve
+    assert rel_max_err(host(p), host(plan.solve(dev(f), rho=dev(rho), p_prev=dev(pp)))) == 0.0
+
+
+def test_const_plan_adjoint_is_transpose(gpu):
+    """For the constant-coefficient solve, grad_f = S^T w = V S(V^-1 w)."""
+    spec, g, f, rho, pp, w = _case((16, 12, 9), seed=15)
+    plan = gpu.Plan(gpu.Grid.from_spec(spec), method="const")
+    gr = plan.adjoint(dev(w))
+    vol = g.volume_field()
+    ref = vol * O.solve_const(w / vol, g)[0]
+    assert rel_max_err(host(gr["f"]), ref) <= 1e-10
+    # <w, S v> == <S^T w, v>
+    v = np.random.default_rng(5).standard_normal(f.shape)
+    sv = host(plan.solve(dev(v)))
+    assert np.isclose((w * sv).sum(), (host(gr["f"]) * v).sum(), rtol=1e-10)

@@ -1,0 +1,154 @@
+"""GPU parity of the FP64 and mixed-precision solves against the FP64 oracle,
+through the C ABI.
+
+Tolerances (FP64 path): one step is an exact linear solve; the GPU uses FFTs
+(O(log N) rounding growth), the oracle matrix-form DFTs (O(N) growth), so the
+two agree to a small multiple of N eps in the max norm relative to max|p|
+(N <= 512 here: bound 1e-11). The residual of each step's constant-
+coefficient system is gated at relres <= 1e-12 (FP64) and <= 1e-10 (mixed).
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from tests.gpu_util import dev, host, oracle_inputs, rel_max_err, say
+
+pytestmark = pytest.mark.gpu
+
+TOL_FP64 = 1e-11
+
+
+def test_const32_manufactured_and_divergence_rhs(gpu):
+    """32^3 constant coefficient: RHS = div(u) + manufactured cos mode."""
+    case = W.const32()
+    g, f, _, _ = oracle_inputs(case)
+    say(f"const32 {g.shape}")
+    plan = gpu.Plan(gpu.Grid.from_spec(case.grid), method="const")
+    p, info = plan.solve(dev(f), info=True)
+    (po,), (oi,) = O.solve(f, g)
+    err = rel_max_err(host(p), po)
+    say(f"  err {err:.3e} relres {info.relres:.3e} (oracle {oi.relres:.3e})")
+    assert err <= TOL_FP64
+    assert info.relres <= 1e-12
+    assert abs(info.rhs_mean_removed) < 1e-12
+    # the manufactured mode alone is an exact eigenvector: p = M / Lambda
+    M = case.extra_rhs
+    lam = (-4 * np.sin(np.pi * 1 / 32) ** 2 - 4 * np.sin(np.pi * 2 / 32) ** 2
+           - 4 * np.sin(np.pi * 3 / 64) ** 2) * 32 ** 2
+    pm = host(plan.solve(dev(M)))
+    assert rel_max_err(pm, M / lam) <= 1e-13
+
+
+SHAPES = [
+    ((12, 18, 10), True),   # radix 3 in x (M = 6) and y; stretched z
+    ((32, 48, 17), False),  # odd nz
+    ((96, 64, 24), True),   # 96 = 3 * 32
+    ((8, 6, 2), False),     # smallest z
+    ((64, 32, 40), True),
+]
+
+
+@pytest.mark.parametrize("shape,stretched", SHAPES)
+def test_method1_chain_small(gpu, shape, stretched):
+    nx, ny, nz = shape
+    lz = 1.3
+    spec = W.GridSpec(nx, ny, nz, 1.0, 0.9, lz, W.tanh_faces(nz, lz, 1.5) if stretched else None)
+    case = W.two_phase_case("small", spec, 1, 7, n_spheres=4)
+    g, f, rho, pp = oracle_inputs(case)
+    say(f"method1 {shape} stretched={stretched}")
+    plan = gpu.Plan(gpu.Grid.from_spec(spec))
+    ps, infos = O.solve(f, g, rho, pp, n_steps=3)
+    for s in (1, 2, 3):
+        p, info = plan.solve(dev(f), rho=dev(rho), p_prev=dev(pp), n_steps=s, info=True)
+        err = rel_max_err(host(p), ps[s - 1])
+        say(f"  step {s}: err {err:.3e} relres {info.relres:.3e} rho0 {info.rho0_used}")
+        assert err <= TOL_FP64
+        assert info.relres <= 1e-12
+        assert info.rho0_used == float(rho.min())
+
+
+def test_method1_constant_density_equals_const_solve(gpu):
+    """rho = const makes beta = 0: one step equals S(rho0 f) whatever p_prev."""
+    spec = W.GridSpec(16, 24, 12, 1.0, 1.0, 1.0, W.tanh_faces(12, 1.0, 1.5))
+    r = np.random.default_rng(3)
+    f = r.standard_normal(spec.nz * spec.ny * spec.nx).reshape(12, 24, 16)
+    pp = r.standard_normal(f.shape)
+    rho = np.full(f.shape, 2.5)
+    gm = gpu.Grid.from_spec(spec)
+    p1 = host(gpu.Plan(gm).solve(dev(f), rho=dev(rho), p_prev=dev(pp)))
+    p2 = host(gpu.Plan(gm, method="const").solve(dev(2.5 * f)))
+    assert rel_max_err(p1, p2) <= 1e-13
+
+
+def test_vd128_ten_step_chain(gpu):
+    """128^3, 20 spheres, rho_l = 1000, 10 chained Method-I steps: per-step parity."""
+    case = W.vd128()
+    g, f, rho, pp = oracle_inputs(case)
+    say("vd128 chain")
+    plan = gpu.Plan(gpu.Grid.from_spec(case.grid))
+    fd, rd, pd = dev(f), dev(rho), dev(pp)
+    ps, infos = O.solve(f, g, rho, pp, n_steps=10, with_relres=False)
+    for s in (1, 2, 10):
+        p, info = plan.solve(fd, rho=rd, p_prev=pd, n_steps=s, info=True)
+        err = rel_max_err(host(p), ps[s - 1])
+        say(f"  step {s}: err {err:.3e} relres {info.relres:.3e}")
+        assert err <= TOL_FP64
+        assert info.relres <= 1e-12
+    # in-place chaining (p_prev aliases p_out) gives the same iterate
+    q = pd.clone()
+    plan.solve(fd, rho=rd, p_prev=q, n_steps=10, out=q)
+    assert rel_max_err(host(q), ps[9]) <= TOL_FP64
+
+
+@pytest.mark.parametrize("shape", [(64, 64, 128), (96, 48, 64)])
+def test_mixed_refinement_small(gpu, shape):
+    nx, ny, nz = shape
+    spec = W.GridSpec(nx, ny, nz, 1.0, 1.0, 2.0, W.tanh_faces(nz, 2.0, 1.5))
+    case = W.two_phase_case("mixed_small", spec, 2, 5, n_spheres=30)
+    g, f, rho, pp = oracle_inputs(case)
+    say(f"mixed {shape}")
+    plan = gpu.Plan(gpu.Grid.from_spec(spec), precision="mixed", tol=1e-10)
+    p, info = plan.solve(dev(f), rho=dev(rho), p_prev=dev(pp), info=True)
+    (po,), (oi,) = O.solve(f, g, rho, pp)
+    err = rel_max_err(host(p), po)
+    rr = O.relres(O.assemble_method1(f, rho, pp, float(rho.min()), g), host(p), g)[0]
+    say(f"  err {err:.3e} relres {info.relres:.3e} (host recheck {rr:.3e}) steps {info.refine_steps}")
+    assert info.relres <= 1e-10
+    assert rr <= 1e-10
+    assert 1 <= info.refine_steps <= 3
+    assert err <= 1e-8
+
+
+def test_density_and_divergence_kernels(gpu):
+    spec = W.GridSpec(24, 16, 10, 1.0, 1.0, 1.0, W.tanh_faces(10, 1.0, 1.5))
+    case = W.two_phase_case("aux", spec, 1, 3, n_spheres=5)
+    g = O.Grid.from_spec(spec)
+    plan = gpu.Plan(gpu.Grid.from_spec(spec))
+    rho = host(plan.density_from_colour(dev(case.phi), dev(case.rho_gas), case.rho_liq))
+    assert rel_max_err(rho, O.mixture_density(case.phi, case.rho_gas, case.rho_liq)) <= 1e-15
+    div = host(plan.divergence(*(dev(u) for u in case.faces)))
+    ref = O.divergence_of_faces(*case.faces, g)
+    assert np.abs(div - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+def test_input_checks(gpu):
+    import paper_2005_11806_amd as psv
+    spec = W.uniform_grid(8, 8, 8)
+    plan = gpu.Plan(gpu.Grid.from_spec(spec), check_inputs=True)
+    f = np.zeros(spec.nz * 64).reshape(8, 8, 8)
+    rho = np.ones_like(f)
+    f_bad = f.copy()
+    f_bad[3, 2, 1] = np.nan
+    with pytest.raises(psv.PsvError) as e:
+        plan.solve(dev(f_bad), rho=dev(rho))
+    assert e.value.status == psv._abi.PSV_ERR_NONFINITE
+    r_bad = rho.copy()
+    r_bad[0, 0, 0] = -1.0
+    with pytest.raises(psv.PsvError) as e:
+        plan.solve(dev(f), rho=dev(r_bad))
+    assert e.value.status == psv._abi.PSV_ERR_INVALID_ARG
+    with pytest.raises(psv.PsvError) as e:
+        plan.solve(dev(f), rho=dev(rho), rho0=2.0)
+    assert e.value.status == psv._abi.PSV_ERR_INVALID_ARG
+    plan.solve(dev(f), rho=dev(rho))  # valid inputs still pass
