@@ -160,6 +160,90 @@ __device__ C* lds_fft(C* buf0, C* buf1, int L, int nlines, int lstride, const Ra
     return src;
 }
 
+// ---------------------------------------------------------------------------
+// Compile-time variant: the line length N (2^a 3^b) and hence every radix,
+// stride and twiddle step are constants. Blocks have 256 threads. Twiddles
+// come from `tw` (usually an LDS copy) holding exp(-2 pi i t / (N * TWM)).
+struct RadixList {
+    int count;
+    int r[12];
+};
+
+__host__ __device__ constexpr RadixList radix_list(int n) {
+    RadixList L{0, {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0}};
+    int a = 0, b = 0, m = n;
+    while (m % 2 == 0) { m /= 2; ++a; }
+    while (m % 3 == 0) { m /= 3; ++b; }
+    while (a >= 3) { L.r[L.count++] = 8; a -= 3; }
+    if (a == 2) L.r[L.count++] = 4;
+    if (a == 1) L.r[L.count++] = 2;
+    while (b-- > 0) L.r[L.count++] = 3;
+    return L;
+}
+
+__host__ __device__ constexpr int radix_prefix(RadixList L, int s) {
+    int p = 1;
+    for (int i = 0; i < s; ++i) p *= L.r[i];
+    return p;
+}
+
+template <int R, int DIR, int NS, int NB, int TSTEP, typename C>
+__device__ __forceinline__ void stockham_bfly_ct(const C* __restrict__ in, C* __restrict__ out,
+                                                 int j, const C* __restrict__ tw) {
+    C v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = in[j + r * NB];
+    const int k = j % NS;
+    if (NS > 1) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+            C w = tw[r * k * TSTEP];
+            if (DIR > 0) w.y = -w.y;
+            v[r] = cmul(v[r], w);
+        }
+    }
+    if (R == 2) bfly2<DIR>(v);
+    if (R == 3) bfly3<DIR>(v);
+    if (R == 4) bfly4<DIR>(v);
+    if (R == 8) bfly8<DIR>(v);
+    const int base = (j / NS) * NS * R + k;
+#pragma unroll
+    for (int r = 0; r < R; ++r) out[base + r * NS] = v[r];
+}
+
+template <int N, int S, int DIR, int TWM, typename C>
+__device__ __forceinline__ C* fft_stages(C* src, C* dst, int nlines, int lstride,
+                                         const C* __restrict__ tw) {
+    constexpr RadixList RL = radix_list(N);
+    if constexpr (S == RL.count) {
+        return src;
+    } else {
+        constexpr int R = RL.r[S];
+        constexpr int NS = radix_prefix(RL, S);
+        constexpr int NB = N / R;
+        constexpr int TSTEP = (N / (NS * R)) * TWM;
+        const int total = nlines * NB;
+        for (int t = threadIdx.x; t < total; t += 256) {
+            const int line = t / NB;
+            const int j = t - line * NB;
+            stockham_bfly_ct<R, DIR, NS, NB, TSTEP>(src + line * lstride, dst + line * lstride, j, tw);
+        }
+        __syncthreads();
+        return fft_stages<N, S + 1, DIR, TWM>(dst, src, nlines, lstride, tw);
+    }
+}
+
+// N = 0 selects the runtime-length routine above.
+template <int N, int DIR, int TWM, typename C>
+__device__ __forceinline__ C* lds_fft_n(C* buf0, C* buf1, int L, int nlines, int lstride,
+                                        const Radices& rp, const C* __restrict__ tw) {
+    if constexpr (N > 0) {
+        return fft_stages<N, 0, DIR, TWM>(buf0, buf1, nlines, lstride, tw);
+    } else {
+        return lds_fft<DIR>(buf0, buf1, L, nlines, lstride, rp, tw, L * TWM);
+    }
+}
+
 // Block-wide sum of one double per thread (blockDim.x <= 1024, multiple of 64).
 __device__ inline double block_sum(double v, double* sh) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);

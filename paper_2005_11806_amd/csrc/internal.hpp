@@ -65,6 +65,7 @@ struct DevTables {
     double* inv_h = nullptr; // [nz]
     double* inv_g = nullptr; // [nz+1], face k between cells k-1 and k (walls: 0)
     double* h = nullptr;     // [nz]
+    double* g = nullptr;     // [nz+1] centre gaps (g[0] = g[nz] = 0)
     double* vol = nullptr;   // [nz]
     double* inv_vol = nullptr;
 };
@@ -118,8 +119,8 @@ struct Plan {
     Launch lp;
     int device = 0;
     // workspace
-    void* spec = nullptr;      // [nz][mx][ny] complex, FP64 or FP32
-    void* cp = nullptr;        // Thomas pivots scratch [nz][mx][ny] (same real type)
+    void* spec = nullptr;      // layout A [nz][mx][ny] complex, FP64 or FP32
+    void* spec_t = nullptr;    // layout B [mx][ny][nz]: one wall-normal system per column
     double* r_ws = nullptr;    // FP64 right-hand side [N]
     double* partials = nullptr;
     int n_partials = 0;

@@ -101,9 +101,10 @@ __device__ __forceinline__ double lap_cell(const double* __restrict__ p, int i, 
     return acc + (ft - fb) * st.inv_h[k];
 }
 
-template <typename TC, typename TS, int MODE>
+// N = nx/2 as a compile-time constant, or 0 for the runtime-length FFT.
+template <typename TC, typename TS, int MODE, int N>
 __global__ void __launch_bounds__(256) k_fwd_x(XGeom g, Stencil st, FwdArgs a,
-                                                const c2<TC>* __restrict__ tw,
+                                                const c2<TC>* __restrict__ tw_g,
                                                 c2<TS>* __restrict__ spec) {
     using C = c2<TC>;
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -112,9 +113,11 @@ __global__ void __launch_bounds__(256) k_fwd_x(XGeom g, Stencil st, FwdArgs a,
     const int b = xcd_remap(blockIdx.x, nb);
     const int k = b / g.tiles;
     const int j0 = (b - k * g.tiles) * g.lb;
-    const int M = g.M;
+    const int M = N ? N : g.M;
     C* buf0 = reinterpret_cast<C*>(smem_raw);
     C* buf1 = buf0 + g.lb * M;
+    C* tw = buf1 + g.lb * M;  // exp(-2 pi i t / nx), t < nx
+    for (int t = threadIdx.x; t < 2 * M; t += blockDim.x) tw[t] = tw_g[t];
     TC* rbuf = reinterpret_cast<TC*>(buf0);
     __shared__ double red[16];
 
@@ -159,7 +162,7 @@ __global__ void __launch_bounds__(256) k_fwd_x(XGeom g, Stencil st, FwdArgs a,
         }
     }
     __syncthreads();
-    C* Z = lds_fft<-1>(buf0, buf1, M, g.lb, M, g.rad, tw, g.nx);
+    C* Z = lds_fft_n<N, -1, 2>(buf0, buf1, M, g.lb, M, g.rad, tw);
     // Split the half-length transform into the real-input spectrum:
     //   E_m = (Z_m + conj Z_{M-m}) / 2, O_m = (Z_m - conj Z_{M-m}) / (2i),
     //   X_m = E_m + exp(-2 pi i m / nx) O_m, m = 0..M.
@@ -177,8 +180,8 @@ __global__ void __launch_bounds__(256) k_fwd_x(XGeom g, Stencil st, FwdArgs a,
     }
 }
 
-template <typename TC, typename TS, int MODE>
-__global__ void __launch_bounds__(256) k_inv_x(XGeom g, const c2<TC>* __restrict__ tw,
+template <typename TC, typename TS, int MODE, int N>
+__global__ void __launch_bounds__(256) k_inv_x(XGeom g, const c2<TC>* __restrict__ tw_g,
                                                 const c2<TS>* __restrict__ spec,
                                                 double* __restrict__ out,
                                                 const double* __restrict__ vol, double scale,
@@ -190,9 +193,11 @@ __global__ void __launch_bounds__(256) k_inv_x(XGeom g, const c2<TC>* __restrict
     const int b = xcd_remap(blockIdx.x, nb);
     const int k = b / g.tiles;
     const int j0 = (b - k * g.tiles) * g.lb;
-    const int M = g.M;
+    const int M = N ? N : g.M;
     C* buf0 = reinterpret_cast<C*>(smem_raw);
     C* xb = buf0 + g.lb * M;  // lb x (M+1), later reused as the FFT's second buffer
+    C* tw = xb + g.lb * (M + 1);
+    for (int t = threadIdx.x; t < 2 * M; t += blockDim.x) tw[t] = tw_g[t];
     const size_t plane_s = (size_t)g.mx * g.ny;
     const int nin = (M + 1) * g.lb;
     for (int t = threadIdx.x; t < nin; t += blockDim.x) {
@@ -217,7 +222,7 @@ __global__ void __launch_bounds__(256) k_inv_x(XGeom g, const c2<TC>* __restrict
         buf0[line * M + m] = C{e.x - o.y, e.y + o.x};
     }
     __syncthreads();
-    C* z = lds_fft<+1>(buf0, xb, M, g.lb, M, g.rad, tw, g.nx);
+    C* z = lds_fft_n<N, +1, 2>(buf0, xb, M, g.lb, M, g.rad, tw);
     const double s = (MODE == INV_SCALE) ? scale * vol[k] : scale;
     const int ncell = g.lb * g.nx;
     for (int t = threadIdx.x; t < ncell; t += blockDim.x) {
@@ -248,34 +253,59 @@ XGeom make_geom(const Plan& p) {
     return g;
 }
 
+// x-line lengths with a compile-time FFT (M = nx/2); others use the runtime one
+#define PSV_X_SIZES(X) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(512)
+
+template <typename TC, typename TS, int MODE, int N>
+void fwd_launch(const Plan& p, const XGeom& g, const Stencil& st, const FwdArgs& a, const c2<TC>* tw,
+                hipStream_t s) {
+    const int nblk = g.tiles * p.nz;
+    const size_t lds = ((size_t)2 * g.lb * g.M + 2 * g.M) * sizeof(c2<TC>);
+    hipLaunchKernelGGL((k_fwd_x<TC, TS, MODE, N>), dim3(nblk), dim3(256), lds, s, g, st, a, tw,
+                       reinterpret_cast<c2<TS>*>(p.spec));
+}
+
 template <typename TC, typename TS, int MODE>
 void fwd_impl(const Plan& p, const FwdArgs& a, hipStream_t s) {
     XGeom g = make_geom(p);
     Stencil st{p.t.inv_h, p.t.inv_g, p.t.vol};
-    const int nblk = g.tiles * p.nz;
-    const size_t lds = (size_t)2 * g.lb * g.M * sizeof(c2<TC>);
     const c2<TC>* tw;
     if constexpr (sizeof(TC) == 8) tw = p.t.twx64; else tw = p.t.twx32;
     static const char* names[2][3] = {{"fwd_x_const_fp64", "fwd_x_method1_fp64", "fwd_x_resid_fp64"},
                                       {"fwd_x_const_fp32", "fwd_x_method1_fp32", "fwd_x_resid_fp32"}};
     TraceScope ts(p, names[sizeof(TC) == 4][MODE], s);
-    hipLaunchKernelGGL((k_fwd_x<TC, TS, MODE>), dim3(nblk), dim3(p.lp.thr_x), lds, s, g, st, a, tw,
-                       reinterpret_cast<c2<TS>*>(p.spec));
+    switch (g.M) {
+#define PSV_CASE(n) case n: fwd_launch<TC, TS, MODE, n>(p, g, st, a, tw, s); break;
+        PSV_X_SIZES(PSV_CASE)
+#undef PSV_CASE
+        default: fwd_launch<TC, TS, MODE, 0>(p, g, st, a, tw, s); break;
+    }
     PSV_HIP(hipGetLastError());
+}
+
+template <typename TC, typename TS, int MODE, int N>
+void inv_launch(const Plan& p, const XGeom& g, const c2<TC>* tw, double* out, double scale,
+                const int* done, hipStream_t s) {
+    const int nblk = g.tiles * p.nz;
+    const size_t lds = ((size_t)g.lb * (2 * g.M + 1) + 2 * g.M) * sizeof(c2<TC>);
+    hipLaunchKernelGGL((k_inv_x<TC, TS, MODE, N>), dim3(nblk), dim3(256), lds, s, g, tw,
+                       reinterpret_cast<const c2<TS>*>(p.spec), out, p.t.vol, scale, done);
 }
 
 template <typename TC, typename TS, int MODE>
 void inv_impl(const Plan& p, double* out, double scale, const int* done, hipStream_t s) {
     XGeom g = make_geom(p);
-    const int nblk = g.tiles * p.nz;
-    const size_t lds = (size_t)g.lb * (2 * g.M + 1) * sizeof(c2<TC>);
     const c2<TC>* tw;
     if constexpr (sizeof(TC) == 8) tw = p.t.twx64; else tw = p.t.twx32;
     static const char* names[2][3] = {{"inv_x_store_fp64", "inv_x_add_fp64", "inv_x_scale_fp64"},
                                       {"inv_x_store_fp32", "inv_x_add_fp32", "inv_x_scale_fp32"}};
     TraceScope ts(p, names[sizeof(TC) == 4][MODE], s);
-    hipLaunchKernelGGL((k_inv_x<TC, TS, MODE>), dim3(nblk), dim3(p.lp.thr_x), lds, s, g, tw,
-                       reinterpret_cast<const c2<TS>*>(p.spec), out, p.t.vol, scale, done);
+    switch (g.M) {
+#define PSV_CASE(n) case n: inv_launch<TC, TS, MODE, n>(p, g, tw, out, scale, done, s); break;
+        PSV_X_SIZES(PSV_CASE)
+#undef PSV_CASE
+        default: inv_launch<TC, TS, MODE, 0>(p, g, tw, out, scale, done, s); break;
+    }
     PSV_HIP(hipGetLastError());
 }
 

@@ -189,10 +189,13 @@ void plan_init(Plan& p, const psv_grid& g, const psv_opts& o, bool alloc_ws) {
     int lds_max = 0;
     PSV_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, p.device));
     const size_t budget = (size_t)std::min(lds_max, 64 * 1024) - 2048;
-    p.lp.lbx = pick_lines(p.ny, (size_t)(p.nx + 1) * sizeof(double2), budget, 16);
-    p.lp.lby = pick_lines(1 << 20, (size_t)2 * p.ny * sizeof(double2), budget, 16);
-    if ((size_t)p.lp.lbx * (p.nx + 1) * sizeof(double2) > budget ||
-        (size_t)p.lp.lby * 2 * p.ny * sizeof(double2) > budget)
+    // (the twiddle table of each direction also lives in LDS)
+    const size_t bx = budget - (size_t)p.nx * sizeof(double2);
+    const size_t by = budget - (size_t)p.ny * sizeof(double2);
+    p.lp.lbx = pick_lines(p.ny, (size_t)(p.nx + 1) * sizeof(double2), bx, 16);
+    p.lp.lby = pick_lines(1 << 20, (size_t)2 * (p.ny + 1) * sizeof(double2), by, 16);
+    if ((size_t)p.lp.lbx * (p.nx + 1) * sizeof(double2) > bx ||
+        (size_t)p.lp.lby * 2 * (p.ny + 1) * sizeof(double2) > by)
         fail(PSV_ERR_UNSUPPORTED_SIZE, "line length exceeds the LDS budget");
 
     p.t.twx64 = upload(tx64);
@@ -207,6 +210,7 @@ void plan_init(Plan& p, const psv_grid& g, const psv_opts& o, bool alloc_ws) {
     p.t.inv_h = upload(inv_h);
     p.t.inv_g = upload(inv_g);
     p.t.h = upload(p.h);
+    p.t.g = upload(p.g);
     p.t.vol = upload(vol);
     p.t.inv_vol = upload(inv_vol);
     // per-block partial sums: 2 per forward-x block, or the reductions' 1.5 * 1024
@@ -219,10 +223,10 @@ void plan_init(Plan& p, const psv_grid& g, const psv_opts& o, bool alloc_ws) {
     PSV_HIP(hipHostMalloc(&p.host_scal, S_NSCAL * sizeof(double)));
     PSV_HIP(hipHostMalloc(&p.host_flags, F_NFLAG * sizeof(int)));
     const size_t nspec = p.nspec(), ncell = p.ncell();
-    p.ws_bytes = nspec * sizeof(double2) + nspec * sizeof(double) + 2 * ncell * sizeof(double);
+    p.ws_bytes = 2 * nspec * sizeof(double2) + 2 * ncell * sizeof(double);
     if (alloc_ws) {
         PSV_HIP(hipMalloc(&p.spec, nspec * sizeof(double2)));
-        PSV_HIP(hipMalloc(&p.cp, nspec * sizeof(double)));
+        PSV_HIP(hipMalloc(&p.spec_t, nspec * sizeof(double2)));
         PSV_HIP(hipMalloc(&p.r_ws, 2 * ncell * sizeof(double)));
         p.own_ws = true;
     }
@@ -230,13 +234,13 @@ void plan_init(Plan& p, const psv_grid& g, const psv_opts& o, bool alloc_ws) {
 
 void plan_free(Plan& p) {
     void* ptrs[] = {p.t.twx64, p.t.twx32, p.t.twy64, p.t.twy32, p.t.lamx, p.t.lamy, p.t.za,
-                    p.t.zb, p.t.zc, p.t.inv_h, p.t.inv_g, p.t.h, p.t.vol, p.t.inv_vol,
+                    p.t.zb, p.t.zc, p.t.inv_h, p.t.inv_g, p.t.h, p.t.g, p.t.vol, p.t.inv_vol,
                     p.partials, p.scal, p.flags};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     if (p.own_ws) {
         if (p.spec) (void)hipFree(p.spec);
-        if (p.cp) (void)hipFree(p.cp);
+        if (p.spec_t) (void)hipFree(p.spec_t);
         if (p.r_ws) (void)hipFree(p.r_ws);
     }
     if (p.host_scal) (void)hipHostFree(p.host_scal);
