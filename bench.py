@@ -33,6 +33,7 @@ if ROOT not in sys.path:
 
 METRIC = "pressure-solve grid pts/s + HBM GB/s % peak; mixed/batched vs FP64 GPU at fixed residual"
 HBM_PEAK_GBS = 8000.0
+COPY_PROBE_BYTES = 256 << 20
 
 WORKLOADS = {
     "vd128": dict(desc="128^3 uniform, Method I (rho0=min rho), 20 spheres, rho_l=1000, rho_g=1-5, "
@@ -91,18 +92,81 @@ def source_digest():
     return h.hexdigest()[:16]
 
 
+def traffic_path(workload):
+    return os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+
+
 def measured_traffic(kernel, workload):
-    """HBM bytes per launch from committed rocprofv3 counter runs
-    (profiles/traffic_<kernel>_<workload>.json), if taken on the current
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    runs (profiles/traffic_<workload>.json), if they were taken on the current
     kernel sources; else None."""
-    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
+    path = traffic_path(workload)
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         t = json.load(fh)
     if t.get("source_digest") != source_digest():
         return None
-    return t.get("bytes_per_launch")
+    k = t.get("kernels", {}).get(kernel)
+    return None if k is None else k["bytes_per_launch"]
+
+
+def trace_name(rocprof_name):
+    """Library trace name of a rocprofv3 kernel name (None if not ours)."""
+    n = rocprof_name
+    prec = "fp32" if "<float" in n else "fp64"
+    if "k_fwd_x<" in n:
+        mode = n.split("k_fwd_x<")[1].split(",")[2].strip()
+        return f"fwd_x_{['const', 'method1', 'resid'][int(mode)]}_{prec}"
+    if "k_inv_x<" in n:
+        mode = n.split("k_inv_x<")[1].split(",")[2].strip()
+        return f"inv_x_{['store', 'add', 'scale'][int(mode)]}_{prec}"
+    if "k_fft_y_t<" in n:
+        d = n.split("k_fft_y_t<")[1].split(",")[2].strip()
+        return f"fft_y_{'fwd' if d.startswith('-') else 'inv'}_{prec}"
+    if "k_tri_wave<" in n:
+        return f"thomas_z_{prec}"
+    if "k_min_partial" in n or "k_min_final" in n:
+        return "min_rho"
+    if "k_residual" in n:
+        return "residual_fp64"
+    return None
+
+
+def ingest_pmc(fetch_csv, write_csv, workload, command):
+    """Writes profiles/traffic_<workload>.json from two rocprofv3 --pmc runs
+    (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) of `bench.py --copy-probe`:
+    each counter is scaled by what it reads for the 256 MiB device copy."""
+    import csv
+    import collections
+    out = {"source_digest": source_digest(), "workload": workload, "command": command,
+           "counters": "rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE (KiB per dispatch)", "kernels": {}}
+    per_launch = {}
+    for path, key in ((fetch_csv, "fetch"), (write_csv, "write")):
+        probe = []
+        # library launches are named by trace name; min_rho is two dispatches
+        sums = collections.defaultdict(float)
+        counts = collections.defaultdict(int)
+        for r in csv.DictReader(open(path)):
+            v = float(r["Counter_Value"]) * 1024.0
+            if "copyBuffer" in r["Kernel_Name"] and int(r["Grid_Size"]) >= 65536:
+                probe.append(v)
+            name = trace_name(r["Kernel_Name"])
+            if name:
+                sums[name] += v
+                if "k_min_final" not in r["Kernel_Name"]:
+                    counts[name] += 1
+        scale = COPY_PROBE_BYTES / (sum(probe) / len(probe))
+        out[f"{key}_scale"] = scale
+        for name in sums:
+            per_launch.setdefault(name, {})[key] = sums[name] * scale / counts[name]
+    for name, d in per_launch.items():
+        f, w = d.get("fetch", 0.0), d.get("write", 0.0)
+        out["kernels"][name] = {"fetch_bytes_per_launch": f, "write_bytes_per_launch": w,
+                                "bytes_per_launch": f + w}
+    with open(traffic_path(workload), "w") as fh:
+        json.dump(out, fh, indent=1, sort_keys=True)
+    print(json.dumps(out["kernels"], indent=1))
 
 
 def blas_threads():
@@ -148,7 +212,15 @@ def main():
     ap.add_argument("--workload", default="vd128", choices=sorted(WORKLOADS))
     ap.add_argument("--mode", default="graph", choices=["graph", "eager"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="first run 3 plain device copies of 256 MiB (counter calibration)")
+    ap.add_argument("--ingest-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write profiles/traffic_<workload>.json from two counter runs and exit")
+    ap.add_argument("--pmc-command", default="", help="command recorded with --ingest-pmc")
     args = ap.parse_args()
+    if args.ingest_pmc:
+        ingest_pmc(args.ingest_pmc[0], args.ingest_pmc[1], args.workload, args.pmc_command)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); this build has no "
               "multi-GPU path", file=sys.stderr)
@@ -156,6 +228,14 @@ def main():
 
     import torch
     import paper_2005_11806_amd as psv
+
+    if args.copy_probe:
+        a = torch.ones(COPY_PROBE_BYTES // 8, dtype=torch.float64, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
 
     wl = WORKLOADS[args.workload]
     case = make_case(args.workload)
