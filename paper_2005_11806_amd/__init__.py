@@ -19,7 +19,8 @@ import numpy as np
 from . import _abi
 from ._abi import PsvError, check
 
-__all__ = ["Grid", "Plan", "SolveInfo", "PsvError", "lib", "PressureSolve", "pressure_solve"]
+__all__ = ["Grid", "Plan", "Batch", "SolveInfo", "PsvError", "lib", "PressureSolve",
+           "pressure_solve"]
 
 
 def lib():
@@ -220,6 +221,68 @@ class Plan:
         check(lib().psv_relres(self._h, _ptr(r, self.shape, "r"), _ptr(p, self.shape, "p"),
                                _stream(stream), C.byref(v)))
         return v.value
+
+
+class Batch:
+    """Uneven batch of independent problems solved together (psv_batch_*):
+    one grid per problem, same options for all; replayed from a HIP graph."""
+
+    def __init__(self, grids, precision="mixed", method="method1", tol=1e-10, max_refine=4):
+        self.grids = list(grids)
+        n = len(self.grids)
+        arr = (_abi.psv_grid * n)()
+        self._keep = []
+        for i, g in enumerate(self.grids):
+            c, keep = g._c()
+            arr[i] = c
+            self._keep.append(keep)
+        o = _abi.psv_opts()
+        lib().psv_opts_default(C.byref(o))
+        o.precision = _PREC[precision]
+        o.method = _METH[method]
+        o.tol = float(tol)
+        o.max_refine = int(max_refine)
+        h = C.c_void_p()
+        check(lib().psv_batch_create(n, arr, C.byref(o), C.byref(h)))
+        self._h = h
+        self.n = n
+        self.method = method
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            check(lib().psv_batch_destroy(self._h))
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, fs, rhos=None, p_prevs=None, outs=None, rho0s=None, stream=None, info=False):
+        import torch
+        n = self.n
+        if outs is None:
+            outs = [torch.empty(g.shape, dtype=torch.float64, device=fs[i].device)
+                    for i, g in enumerate(self.grids)]
+        P = C.c_void_p * n
+        f_a = P(*[_ptr(fs[i], self.grids[i].shape, "f").value for i in range(n)])
+        o_a = P(*[_ptr(outs[i], self.grids[i].shape, "out").value for i in range(n)])
+        r_a = P(*[_ptr(rhos[i], self.grids[i].shape, "rho").value for i in range(n)]) if rhos else None
+        p_a = P(*[_ptr(p_prevs[i], self.grids[i].shape, "p_prev").value for i in range(n)]) \
+            if p_prevs else None
+        r0 = (C.c_double * n)(*[0.0 if rho0s is None else float(rho0s[i]) for i in range(n)])
+        infos = (_abi.psv_info * n)() if info else None
+        st = lib().psv_batch_solve(self._h, f_a, r_a, r0, p_a, o_a, _stream(stream), infos)
+        if info:
+            out_infos = [SolveInfo(x.refine_steps, x.relres, x.rhs_mean_removed, x.rho0_used)
+                         for x in infos]
+            if st == _abi.PSV_ERR_NOT_CONVERGED:
+                raise PsvError(st, f"not converged: {out_infos}")
+            check(st)
+            return outs, out_infos
+        check(st)
+        return outs
 
 
 from .autograd import PressureSolve, pressure_solve  # noqa: E402

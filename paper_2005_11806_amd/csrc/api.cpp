@@ -14,6 +14,16 @@ void validate_opts(const psv_opts* o);
 void default_opts(psv_opts* o);
 std::string trace_summary(Plan& p);
 void trace_free(Plan& p);
+psv_batch* batch_new();
+void batch_delete(psv_batch* b);
+void batch_create(psv_batch& B, int n, const psv_grid* grids, const psv_opts& o);
+int batch_size(const psv_batch& B);
+int batch_method(const psv_batch& B);
+bool batch_fp32(const psv_batch& B);
+void batch_set_io(psv_batch& B, int p, const double* f, const double* rho, const double* pprev,
+                  double* pout, double rho0, bool want_r);
+void batch_solve(psv_batch& B, hipStream_t s, bool check);
+bool batch_infos(psv_batch& B, hipStream_t s, psv_info* infos);
 }  // namespace psv
 
 struct psv_plan {
@@ -338,17 +348,69 @@ psv_status psv_relres(psv_plan* plan, const double* r, const double* p, void* st
     });
 }
 
-psv_status psv_batch_create(int32_t, const psv_grid*, const psv_opts*, psv_batch** out) {
-    if (out) *out = nullptr;
-    return record(PSV_ERR_INVALID_ARG, "batched solves are not available in this build");
+psv_status psv_batch_create(int32_t n, const psv_grid* grids, const psv_opts* opts,
+                            psv_batch** out) {
+    return guarded([&] {
+        need(out != nullptr, "out is NULL");
+        *out = nullptr;
+        need(n >= 1 && n <= 65536, "n must be in [1, 65536]");
+        need(grids != nullptr, "grids is NULL");
+        for (int p = 0; p < n; ++p) psv::validate_grid(&grids[p]);
+        psv::validate_opts(opts);
+        psv_opts o;
+        if (opts)
+            o = *opts;
+        else
+            psv::default_opts(&o);
+        if (o.tol <= 0.0) o.tol = 1e-10;
+        if (o.max_refine <= 0) o.max_refine = 4;
+        psv_batch* b = psv::batch_new();
+        try {
+            psv::batch_create(*b, n, grids, o);
+        } catch (...) {
+            psv::batch_delete(b);
+            throw;
+        }
+        *out = b;
+    });
 }
 
-psv_status psv_batch_solve(psv_batch*, const double* const*, const double* const*, const double*,
-                           const double* const*, double* const*, void*, psv_info*) {
-    return record(PSV_ERR_INVALID_ARG, "batched solves are not available in this build");
+psv_status psv_batch_solve(psv_batch* batch, const double* const* f, const double* const* rho,
+                           const double* rho0, const double* const* p_prev, double* const* p_out,
+                           void* stream, psv_info* infos) {
+    return guarded([&] {
+        need(batch != nullptr, "batch is NULL");
+        need(f != nullptr && p_out != nullptr, "f and p_out are required");
+        const int n = psv::batch_size(*batch);
+        const bool method1 = psv::batch_method(*batch) == PSV_SPLIT_RHO0;
+        const bool fp32 = psv::batch_fp32(*batch);
+        for (int p = 0; p < n; ++p) {
+            need(f[p] != nullptr && p_out[p] != nullptr, "f[p] and p_out[p] must be non-NULL");
+            if (method1) {
+                need(rho != nullptr && rho[p] != nullptr, "rho[p] is required by Method I");
+                need(p_prev != nullptr && p_prev[p] != nullptr, "p_prev[p] is required by Method I");
+                need(p_prev[p] != p_out[p], "batched solves need p_prev[p] != p_out[p]");
+            }
+            if (rho0) need(std::isfinite(rho0[p]), "rho0 must be finite");
+        }
+        for (int p = 0; p < n; ++p)
+            psv::batch_set_io(*batch, p, f[p], method1 ? rho[p] : nullptr,
+                              method1 ? p_prev[p] : nullptr, p_out[p], rho0 ? rho0[p] : 0.0,
+                              fp32 || infos != nullptr);
+        hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+        psv::batch_solve(*batch, s, fp32 || infos != nullptr);
+        if (infos) {
+            const bool ok = psv::batch_infos(*batch, s, infos);
+            if (!ok) psv::fail(PSV_ERR_NOT_CONVERGED, "a batched problem did not reach tol");
+        }
+    });
 }
 
-psv_status psv_batch_destroy(psv_batch*) { return PSV_OK; }
+psv_status psv_batch_destroy(psv_batch* batch) {
+    return guarded([&] {
+        if (batch) psv::batch_delete(batch);
+    });
+}
 
 psv_status psv_trace_enable(psv_plan* plan, int32_t enable) {
     return guarded([&] {
