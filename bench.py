@@ -204,12 +204,90 @@ def cpu_baseline(case, n_steps_target, budget_s=15.0):
                       f"({g.nx}x{g.ny}x{g.nz}), matrix-form DFT + textbook Thomas, {total:.1f} s"}
 
 
+BATCH_WORKLOADS = {
+    "batch64": ("mixed", "default", "64 problems from {64^3, 96x96x128, 128^3, 128x128x192}, "
+                "Method I, FP32 bulk + FP64 refinement to relres 1e-10, batched per-pass launches "
+                "in one HIP graph"),
+    "batch64_persistent": ("mixed", "persistent", "same 64 problems, FP32 + FP64 refinement, one "
+                           "persistent launch over the task queue in one HIP graph"),
+    "batch64_fp64": ("fp64", "default", "same 64 problems, FP64, batched per-pass launches in one "
+                     "HIP graph"),
+    "batch64_fp64_seq": ("fp64", None, "same 64 problems, FP64, one plan per problem solved in "
+                         "sequence (graph-replayed)"),
+}
+
+
+def bench_batch(args):
+    """Throughput of the 64-problem uneven batch (total grid points per second)."""
+    import torch
+    import paper_2005_11806_amd as psv
+    import workloads as W
+    prec, executor, desc = BATCH_WORKLOADS[args.workload]
+    cases = W.batch()
+    dev = torch.device("cuda:0")
+    to = lambda a: torch.from_numpy(a).to(dev)  # noqa: E731
+    grids = [psv.Grid.from_spec(c.grid) for c in cases]
+    plans = [psv.Plan(g, precision=prec) for g in grids]
+    fs = [pl.divergence(*(to(u) for u in c.faces)) for pl, c in zip(plans, cases)]
+    rs = [pl.density_from_colour(to(c.phi), to(c.rho_gas), c.rho_liq) for pl, c in zip(plans, cases)]
+    ps = [to(c.p_prev) for c in cases]
+    outs = [torch.empty_like(f) for f in fs]
+    ntot = sum(c.grid.n for c in cases)
+    if executor is None:
+        infos = [pl.solve(f, rho=r, p_prev=p, out=o, info=True)[1] for pl, f, r, p, o in
+                 zip(plans, fs, rs, ps, outs)]
+
+        def step():
+            for pl, f, r, p, o in zip(plans, fs, rs, ps, outs):
+                pl.solve(f, rho=r, p_prev=p, out=o)
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            step()
+        torch.cuda.current_stream().wait_stream(s)
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            step()
+        run = graph.replay
+    else:
+        batch = psv.Batch(grids, precision=prec, executor=executor)
+        _, infos = batch.solve(fs, rs, ps, outs, info=True)
+
+        def run():
+            batch.solve(fs, rs, ps, outs)
+    for _ in range(args.warmup):
+        run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        run()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ms = 1e3 * el / args.steps
+    alg = 32.0 * ntot  # f, rho, p_prev in, p out (FP64)
+    ach = alg / (el / args.steps) / 1e9
+    line = {
+        "metric": METRIC, "value": ntot * args.steps / el, "unit": "grid_pts/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64" if prec == "fp64" else "f32+f64",
+        "data": "synthetic (seeded generators in workloads/)",
+        "config": {"workload": f"{args.workload}: {desc}", "problems": len(cases), "cells": ntot,
+                   "max_relres": max(i.relres for i in infos),
+                   "refine_steps": sorted(set(i.refine_steps for i in infos))},
+        "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": ach / HBM_PEAK_GBS, "traffic": None, "kernel": "whole batch",
+                     "algorithmic_bytes": alg},
+        "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="vd128", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="vd128", choices=sorted(WORKLOADS) + sorted(BATCH_WORKLOADS))
     ap.add_argument("--mode", default="graph", choices=["graph", "eager"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
@@ -228,6 +306,10 @@ def main():
 
     import torch
     import paper_2005_11806_amd as psv
+
+    if args.workload in BATCH_WORKLOADS:
+        bench_batch(args)
+        return
 
     if args.copy_probe:
         a = torch.ones(COPY_PROBE_BYTES // 8, dtype=torch.float64, device="cuda:0")

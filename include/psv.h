@@ -81,6 +81,8 @@ typedef struct {
     int32_t max_refine;      /* MIXED: maximum refinement sweeps; <= 0 selects 4 */
     int32_t check_inputs;    /* 1: scan inputs for NaN/Inf and rho <= 0 (synchronises) */
     int32_t autotune;        /* 0: built-in launch shapes; 1: time candidates at plan creation */
+    int32_t batch_executor;  /* batches: 0 default (per-pass launches), 1 per-pass launches,
+                                2 one persistent launch over the task queue */
 } psv_opts;
 
 typedef struct {

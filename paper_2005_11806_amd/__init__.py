@@ -227,7 +227,10 @@ class Batch:
     """Uneven batch of independent problems solved together (psv_batch_*):
     one grid per problem, same options for all; replayed from a HIP graph."""
 
-    def __init__(self, grids, precision="mixed", method="method1", tol=1e-10, max_refine=4):
+    _EXEC = {"default": 0, "passes": 1, "persistent": 2}
+
+    def __init__(self, grids, precision="mixed", method="method1", tol=1e-10, max_refine=4,
+                 executor="default"):
         self.grids = list(grids)
         n = len(self.grids)
         arr = (_abi.psv_grid * n)()
@@ -242,6 +245,7 @@ class Batch:
         o.method = _METH[method]
         o.tol = float(tol)
         o.max_refine = int(max_refine)
+        o.batch_executor = self._EXEC[executor]
         h = C.c_void_p()
         check(lib().psv_batch_create(n, arr, C.byref(o), C.byref(h)))
         self._h = h

@@ -322,6 +322,91 @@ __global__ void __launch_bounds__(256) k_batch_pass(const ProblemDesc* __restric
     run_task<T, KIND>(desc[lo], io[lo], blk - start[lo], smem_raw, red);
 }
 
+// Persistent executor. Tasks are int4 {problem, level, tile, tiles of the
+// previous level of that problem}; the queue holds every level of every
+// problem, level by level, problems largest first, so whatever a task waits
+// for was dequeued earlier by a running block and the wait always ends.
+// A wait that exceeds the spin budget sets *error and the block carries on
+// (the kernel always drains); the host then reports the failure.
+struct PersistArgs {
+    const ProblemDesc* desc;
+    const ProblemIO* io;
+    const int4* tasks;
+    const int* kinds;  // kind of each level
+    int* counters;     // [nprob][nlevels] completed tiles
+    int* ticket;
+    int* error;
+    int ntasks;
+    int nlevels;
+};
+
+constexpr long long SPIN_LIMIT = 1ll << 22;  // x s_sleep(2): well above any legitimate wait
+
+template <typename T>
+__device__ __forceinline__ void run_kind(int kind, const ProblemDesc& D, const ProblemIO& io, int b,
+                                         unsigned char* smem, double* red) {
+    switch (kind) {
+#define PSV_K(k) case k: run_task<T, k>(D, io, b, smem, red); break;
+        PSV_K(K_MINP) PSV_K(K_MINF) PSV_K(K_FWD) PSV_K(K_MEAN) PSV_K(K_Y) PSV_K(K_Z) PSV_K(K_Z2)
+        PSV_K(K_YI) PSV_K(K_INV) PSV_K(K_INVADD) PSV_K(K_RES) PSV_K(K_NRM) PSV_K(K_CHK)
+        PSV_K(K_CHKF)
+#undef PSV_K
+        default: break;
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_batch_persistent(PersistArgs A) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ double red[16];
+    __shared__ int s_task;
+    for (;;) {
+        __syncthreads();  // the previous task is done with LDS and s_task
+        if (threadIdx.x == 0) s_task = atomicAdd(A.ticket, 1);
+        __syncthreads();
+        const int t = s_task;
+        if (t >= A.ntasks) break;
+        const int4 tk = A.tasks[t];
+        int* cnt = A.counters + (size_t)tk.x * A.nlevels;
+        if (threadIdx.x == 0 && tk.y > 0) {
+            long long spins = 0;
+            while (__hip_atomic_load(cnt + tk.y - 1, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < tk.w) {
+                __builtin_amdgcn_s_sleep(2);
+                if (++spins > SPIN_LIMIT) {
+                    atomicOr(A.error, 1);
+                    break;
+                }
+                // once any wait has failed, no block waits again: the drain is bounded
+                if ((spins & 255) == 0 &&
+                    __hip_atomic_load(A.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+                    break;
+            }
+        }
+        __syncthreads();
+        __threadfence();  // every wave observes the producers' writes
+        run_kind<T>(A.kinds[tk.y], A.desc[tk.x], A.io[tk.x], tk.z, smem_raw, red);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            __threadfence();
+            __hip_atomic_fetch_add(cnt + tk.y, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+__global__ void k_persist_reset(ProblemDesc* desc, int n, int* counters, int ncount, int* ticket,
+                                int* error) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        desc[i].flags[F_DONE] = 0;
+        desc[i].flags[F_STEPS] = 0;
+    }
+    if (i < ncount) counters[i] = 0;
+    if (i == 0) {
+        *ticket = 0;
+        *error = 0;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // host
 struct PassLaunch {
@@ -347,7 +432,17 @@ struct psv_batch {
     hipGraph_t graph[2] = {nullptr, nullptr};
     hipGraphExec_t exec[2] = {nullptr, nullptr};
     int device = 0;
-    size_t max_lds = 0;
+    // persistent executor (per graph)
+    int persistent = 0;
+    int4* d_tasks[2] = {nullptr, nullptr};
+    int* d_kinds[2] = {nullptr, nullptr};
+    int ntasks[2] = {0, 0};
+    int nlevels[2] = {0, 0};
+    size_t plds[2] = {0, 0};
+    int* d_counters = nullptr;  // sized for the longer sequence
+    int ncounters = 0;
+    int* d_ticket = nullptr;    // [0] ticket, [1] error
+    int* h_err = nullptr;       // pinned
 };
 
 namespace psv {
@@ -429,9 +524,62 @@ void batch_build(psv_batch& B, bool check) {
         L.d_start = d;
         B.seq[gi].push_back(L);
     }
+    // persistent queue: level by level, problems largest first (LPT)
+    std::vector<int> order(B.n);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        return B.plans[a]->ncell() > B.plans[b]->ncell();
+    });
+    std::vector<int4> tasks;
+    const int nlev = (int)kinds.size();
+    size_t plds = 0;
+    for (int lev = 0; lev < nlev; ++lev) {
+        for (int p : order) {
+            const int nt = kind_tiles(*B.plans[p], kinds[lev]);
+            const int dep = lev > 0 ? kind_tiles(*B.plans[p], kinds[lev - 1]) : 0;
+            for (int t = 0; t < nt; ++t) tasks.push_back(int4{p, lev, t, dep});
+            plds = std::max(plds, kind_lds(*B.plans[p], kinds[lev], B.fp32));
+        }
+    }
+    B.ntasks[gi] = (int)tasks.size();
+    B.nlevels[gi] = nlev;
+    B.plds[gi] = plds;
+    PSV_HIP(hipMalloc(&B.d_tasks[gi], tasks.size() * sizeof(int4)));
+    PSV_HIP(hipMemcpy(B.d_tasks[gi], tasks.data(), tasks.size() * sizeof(int4), hipMemcpyHostToDevice));
+    PSV_HIP(hipMalloc(&B.d_kinds[gi], kinds.size() * sizeof(int)));
+    PSV_HIP(hipMemcpy(B.d_kinds[gi], kinds.data(), kinds.size() * sizeof(int), hipMemcpyHostToDevice));
+    if (B.n * nlev > B.ncounters) {
+        if (B.d_counters) PSV_HIP(hipFree(B.d_counters));
+        B.ncounters = B.n * nlev;
+        PSV_HIP(hipMalloc(&B.d_counters, B.ncounters * sizeof(int)));
+    }
+}
+
+template <typename T>
+static void launch_persistent(const psv_batch& B, int gi, hipStream_t s) {
+    const int ncount = B.n * B.nlevels[gi];
+    const int rn = std::max(B.n, ncount);
+    hipLaunchKernelGGL(k_persist_reset, dim3((rn + 255) / 256), dim3(256), 0, s, B.d_desc, B.n,
+                       B.d_counters, ncount, B.d_ticket, B.d_ticket + 1);
+    int per_cu = 0, ncu = 0;
+    PSV_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_persistent<T>, 256,
+                                                         B.plds[gi]));
+    PSV_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, B.device));
+    const int grid = std::max(1, std::min(per_cu, 8) * ncu);
+    PersistArgs A{B.d_desc, B.d_io, B.d_tasks[gi], B.d_kinds[gi], B.d_counters,
+                  B.d_ticket, B.d_ticket + 1, B.ntasks[gi], B.nlevels[gi]};
+    hipLaunchKernelGGL(k_batch_persistent<T>, dim3(grid), dim3(256), B.plds[gi], s, A);
+    PSV_HIP(hipGetLastError());
 }
 
 void batch_enqueue(const psv_batch& B, int gi, hipStream_t s) {
+    if (B.persistent) {
+        if (B.fp32)
+            launch_persistent<float>(B, gi, s);
+        else
+            launch_persistent<double>(B, gi, s);
+        return;
+    }
     hipLaunchKernelGGL(k_batch_reset, dim3((B.n + 255) / 256), dim3(256), 0, s, B.d_desc, B.n);
     for (const PassLaunch& L : B.seq[gi]) {
         if (B.fp32)
@@ -489,6 +637,10 @@ void batch_create(psv_batch& B, int n, const psv_grid* grids, const psv_opts& o)
     PSV_HIP(hipMalloc(&B.d_io, n * sizeof(ProblemIO)));
     PSV_HIP(hipHostMalloc(&B.h_io, n * sizeof(ProblemIO)));
     std::memset(B.h_io, 0, n * sizeof(ProblemIO));
+    PSV_HIP(hipMalloc(&B.d_ticket, 2 * sizeof(int)));
+    PSV_HIP(hipHostMalloc(&B.h_err, sizeof(int)));
+    *B.h_err = 0;
+    B.persistent = (o.batch_executor == 2) ? 1 : 0;
 }
 
 void batch_free(psv_batch& B) {
@@ -496,8 +648,14 @@ void batch_free(psv_batch& B) {
         if (B.exec[i]) (void)hipGraphExecDestroy(B.exec[i]);
         if (B.graph[i]) (void)hipGraphDestroy(B.graph[i]);
     }
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < 2; ++i) {
         for (int* d : B.starts[i]) (void)hipFree(d);
+        if (B.d_tasks[i]) (void)hipFree(B.d_tasks[i]);
+        if (B.d_kinds[i]) (void)hipFree(B.d_kinds[i]);
+    }
+    if (B.d_counters) (void)hipFree(B.d_counters);
+    if (B.d_ticket) (void)hipFree(B.d_ticket);
+    if (B.h_err) (void)hipHostFree(B.h_err);
     for (Plan* p : B.plans) {
         plan_free(*p);
         delete p;
@@ -551,6 +709,10 @@ void batch_set_io(psv_batch& B, int p, const double* f, const double* rho, const
 // problem missed its tolerance.
 bool batch_infos(psv_batch& B, hipStream_t s, psv_info* infos) {
     PSV_HIP(hipStreamSynchronize(s));
+    if (B.persistent) {
+        PSV_HIP(hipMemcpy(B.h_err, B.d_ticket + 1, sizeof(int), hipMemcpyDeviceToHost));
+        if (*B.h_err) fail(PSV_ERR_HIP, "persistent batch: a dependency wait exceeded its spin budget");
+    }
     bool ok = true;
     for (int p = 0; p < B.n; ++p) {
         Plan& P = *B.plans[p];

@@ -73,6 +73,8 @@ void validate_opts(const psv_opts* o) {
     if (!(o->tol >= 0.0) && !(o->tol < 0.0)) fail(PSV_ERR_INVALID_ARG, "tol is NaN");
     if (o->check_inputs != 0 && o->check_inputs != 1) fail(PSV_ERR_INVALID_ARG, "check_inputs must be 0 or 1");
     if (o->autotune < 0 || o->autotune > 2) fail(PSV_ERR_INVALID_ARG, "autotune must be 0..2");
+    if (o->batch_executor < 0 || o->batch_executor > 2)
+        fail(PSV_ERR_INVALID_ARG, "batch_executor must be 0..2");
 }
 
 void default_opts(psv_opts* o) {
@@ -83,6 +85,7 @@ void default_opts(psv_opts* o) {
     o->max_refine = 4;
     o->check_inputs = 0;
     o->autotune = 0;
+    o->batch_executor = 0;
 }
 
 // exp(-2 pi i t / n), t = 0..n-1, from the angle reduced to the first octant

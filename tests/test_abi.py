@@ -32,7 +32,7 @@ def test_library_exports_every_declared_function():
 
 def test_struct_layouts_match_header():
     assert C.sizeof(_abi.psv_grid) == 3 * 4 + 4 + 3 * 8 + 8 + 8  # ints, pad, doubles, ptr, enum+pad
-    assert C.sizeof(_abi.psv_opts) == 8 + 8 + 4 * 4  # precision, method, tol, 3 ints + pad
+    assert C.sizeof(_abi.psv_opts) == 8 + 8 + 4 * 4  # precision, method, tol, 4 ints
     assert C.sizeof(_abi.psv_info) == 8 + 3 * 8
 
 

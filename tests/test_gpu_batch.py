@@ -25,12 +25,14 @@ def _cases(shapes, seed0=20):
     return out
 
 
+@pytest.mark.parametrize("executor", ["passes", "persistent"])
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-11), ("mixed", 1e-8)])
-def test_small_uneven_batch(gpu, precision, tol):
+def test_small_uneven_batch(gpu, precision, tol, executor):
     cases = _cases(SMALL)
     ins = [oracle_inputs(c) for c in cases]
     grids = [gpu.Grid.from_spec(c.grid) for c in cases]
-    batch = gpu.Batch(grids, precision=precision)
+    say(f"executor {executor}")
+    batch = gpu.Batch(grids, precision=precision, executor=executor)
     fs = [dev(x[1]) for x in ins]
     rs = [dev(x[2]) for x in ins]
     ps = [dev(x[3]) for x in ins]
@@ -67,7 +69,8 @@ def test_batch_explicit_rho0_and_const(gpu):
         assert rel_max_err(host(outs[i]), O.solve_const(f, g)[0]) <= 1e-11
 
 
-def test_batch64_uneven_mixed(gpu):
+@pytest.mark.parametrize("executor", ["passes", "persistent"])
+def test_batch64_uneven_mixed(gpu, executor):
     """64 problems drawn from {64^3, 96x96x128, 128^3, 128x128x192}, mixed
     precision: each matches its standalone mixed solve; a sample of 6 matches
     the FP64 oracle."""
@@ -83,7 +86,8 @@ def test_batch64_uneven_mixed(gpu):
     fs = [dev(x[1]) for x in ins]
     rs = [dev(x[2]) for x in ins]
     ps = [dev(x[3]) for x in ins]
-    batch = gpu.Batch(grids, precision="mixed")
+    batch = gpu.Batch(grids, precision="mixed", executor=executor)
+    say(f"executor {executor}")
     outs, infos = batch.solve(fs, rs, ps, info=True)
     outs, infos = batch.solve(fs, rs, ps, info=True)  # replay
     assert max(i.relres for i in infos) <= 1e-10
