@@ -289,6 +289,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="vd128", choices=sorted(WORKLOADS) + sorted(BATCH_WORKLOADS))
     ap.add_argument("--mode", default="graph", choices=["graph", "eager"])
+    ap.add_argument("--autotune", type=int, default=1, choices=[0, 1],
+                    help="tune launch shapes at plan creation (outside the timed region)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first run 3 plain device copies of 256 MiB (counter calibration)")
@@ -326,7 +328,7 @@ def main():
     to = lambda a: torch.from_numpy(a).to(dev)  # noqa: E731
     const = case.phi is None
     plan = psv.Plan(psv.Grid.from_spec(spec), precision=wl["precision"],
-                    method="const" if const else "method1")
+                    method="const" if const else "method1", autotune=args.autotune)
     f = plan.divergence(*(to(u) for u in case.faces))
     if case.extra_rhs is not None:
         f += to(case.extra_rhs)

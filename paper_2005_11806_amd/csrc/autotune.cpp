@@ -1,0 +1,199 @@
+// Launch-shape autotuner of a plan: lines per x-block (lbx), planes per
+// y-tile (lby) and rows per lane of the tridiagonal solve (tri_L). Each pass is
+// timed with hipEvents on synthetic data for every candidate that fits the LDS
+// budget; the fastest per pass is kept, and the tuned solve must match the
+// default-shape solve (FP64: 1e-10, FP32 spectra: 1e-3 relative in the max
+// norm) or the defaults stay. Choices are cached per (arch, grid, precision,
+// method) in the process and, when PSV_AUTOTUNE_CACHE names a file, on disk
+// (one "key lbx lby tri_L" line per entry).
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <fstream>
+#include <functional>
+#include <map>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "pass_yz.hpp"
+
+namespace psv {
+namespace {
+
+std::mutex g_mu;
+std::map<std::string, Launch> g_cache;
+bool g_loaded = false;
+
+std::string tune_key(const Plan& p) {
+    hipDeviceProp_t prop;
+    PSV_HIP(hipGetDeviceProperties(&prop, p.device));
+    std::ostringstream os;
+    os << prop.gcnArchName << ":" << p.nx << "x" << p.ny << "x" << p.nz << ":"
+       << (p.opts.precision == PSV_MIXED ? "mixed" : "fp64") << ":"
+       << (p.opts.method == PSV_SPLIT_RHO0 ? "method1" : "const");
+    return os.str();
+}
+
+void load_cache() {
+    if (g_loaded) return;
+    g_loaded = true;
+    const char* path = std::getenv("PSV_AUTOTUNE_CACHE");
+    if (!path) return;
+    std::ifstream in(path);
+    std::string key;
+    Launch l;
+    while (in >> key >> l.lbx >> l.lby >> l.tri_L) g_cache[key] = l;
+}
+
+void store_cache(const std::string& key, const Launch& l) {
+    g_cache[key] = l;
+    const char* path = std::getenv("PSV_AUTOTUNE_CACHE");
+    if (!path) return;
+    std::ofstream out(path, std::ios::app);
+    out << key << " " << l.lbx << " " << l.lby << " " << l.tri_L << "\n";
+}
+
+// deterministic synthetic inputs: f, p_prev smooth-ish, rho in [1, 1000]
+__global__ void k_synth(size_t n, double* f, double* rho, double* pp) {
+    for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < n;
+         c += (size_t)gridDim.x * blockDim.x) {
+        unsigned int h = (unsigned int)(c * 2654435761u) ^ 0x9e3779b9u;
+        h ^= h >> 16;
+        h *= 0x85ebca6bu;
+        h ^= h >> 13;
+        const double u = (double)(h & 0xffffff) / 16777216.0;
+        f[c] = u - 0.5;
+        rho[c] = 1.0 + 999.0 * u * u;
+        pp[c] = sin(1e-3 * (double)c);
+    }
+}
+
+float time_ms(hipStream_t s, const std::function<void()>& fn) {
+    hipEvent_t a, b;
+    PSV_HIP(hipEventCreate(&a));
+    PSV_HIP(hipEventCreate(&b));
+    for (int i = 0; i < 2; ++i) fn();
+    PSV_HIP(hipEventRecord(a, s));
+    const int reps = 5;
+    for (int i = 0; i < reps; ++i) fn();
+    PSV_HIP(hipEventRecord(b, s));
+    PSV_HIP(hipEventSynchronize(b));
+    float ms = 0.f;
+    PSV_HIP(hipEventElapsedTime(&ms, a, b));
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    return ms / reps;
+}
+
+void solve_once(const Plan& p, const FwdArgs& a, double* out, hipStream_t s) {
+    const bool fp32 = p.opts.precision == PSV_MIXED;
+    launch_fwd_x(p, fp32, a, s);
+    launch_fft_y(p, fp32, false, nullptr, s);
+    launch_thomas(p, fp32, p.scal + S_MEAN2, nullptr, s);
+    launch_fft_y(p, fp32, true, nullptr, s);
+    launch_inv_x(p, fp32, INV_STORE, out, 2.0 / ((double)p.nx * p.ny), nullptr, s);
+}
+
+bool fits_x(const Plan& p, int lb) {
+    if (p.ny % lb) return false;
+    const size_t bytes = ((size_t)lb * (p.nx + 1) + p.nx) * sizeof(double2);
+    return bytes <= 62 * 1024;
+}
+
+bool fits_y(const Plan& p, int kb) {
+    return ((size_t)2 * kb * (p.ny + 1) + p.ny) * sizeof(double2) <= 62 * 1024;
+}
+
+}  // namespace
+
+void autotune_plan(Plan& p) {
+    std::lock_guard<std::mutex> lock(g_mu);
+    load_cache();
+    const std::string key = tune_key(p);
+    auto it = g_cache.find(key);
+    if (it != g_cache.end()) {
+        if (fits_x(p, it->second.lbx) && fits_y(p, it->second.lby)) {
+            p.lp.lbx = it->second.lbx;
+            p.lp.lby = it->second.lby;
+            p.lp.tri_L = it->second.tri_L;
+            return;
+        }
+    }
+    const bool fp32 = p.opts.precision == PSV_MIXED;
+    const size_t n = p.ncell();
+    double* buf = nullptr;
+    PSV_HIP(hipMalloc(&buf, 5 * n * sizeof(double)));
+    double *f = buf, *rho = buf + n, *pp = buf + 2 * n, *out_ref = buf + 3 * n, *out = buf + 4 * n;
+    hipStream_t s;
+    PSV_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    hipLaunchKernelGGL(k_synth, dim3(1024), dim3(256), 0, s, n, f, rho, pp);
+    launch_set_scalar(p.scal + S_RHO0, 1.0, s);
+    FwdArgs a{};
+    a.mode = p.opts.method == PSV_SPLIT_RHO0 ? FWD_METHOD1 : FWD_CONST;
+    a.f = f;
+    a.rho = rho;
+    a.pprev = pp;
+    a.rho0 = p.scal + S_RHO0;
+    const Launch def = p.lp;
+    solve_once(p, a, out_ref, s);
+
+    Launch best = def;
+    float tbest = 1e30f;
+    for (int lb : {1, 2, 4, 8, 16}) {
+        if (!fits_x(p, lb)) continue;
+        p.lp.lbx = lb;
+        const float t = time_ms(s, [&] { launch_fwd_x(p, fp32, a, s); }) +
+                        time_ms(s, [&] { launch_inv_x(p, fp32, INV_STORE, out, 1.0, nullptr, s); });
+        if (t < tbest) { tbest = t; best.lbx = lb; }
+    }
+    p.lp.lbx = best.lbx;
+    tbest = 1e30f;
+    for (int kb : {1, 2, 4, 8, 16}) {
+        if (!fits_y(p, kb)) continue;
+        p.lp.lby = kb;
+        const float t = time_ms(s, [&] { launch_fft_y(p, fp32, false, nullptr, s); }) +
+                        time_ms(s, [&] { launch_fft_y(p, fp32, true, nullptr, s); });
+        if (t < tbest) { tbest = t; best.lby = kb; }
+    }
+    p.lp.lby = best.lby;
+    tbest = 1e30f;
+    for (int L : {4, 8, 16, 32}) {
+        int Lr = 8, P = 1;
+        tri_shape(p.nz, Lr, P, L);
+        if (Lr != L) continue;  // this L needs more than 64 lanes per system
+        p.lp.tri_L = L;
+        launch_fwd_x(p, fp32, a, s);  // fresh spectrum for every candidate
+        launch_fft_y(p, fp32, false, nullptr, s);
+        const float t = time_ms(s, [&] { launch_thomas(p, fp32, p.scal + S_MEAN2, nullptr, s); });
+        if (t < tbest) { tbest = t; best.tri_L = L; }
+    }
+    p.lp = best;
+    // parity of the tuned shapes against the default ones
+    solve_once(p, a, out, s);
+    PSV_HIP(hipStreamSynchronize(s));
+    std::vector<double> h_ref(n), h_out(n);
+    PSV_HIP(hipMemcpy(h_ref.data(), out_ref, n * sizeof(double), hipMemcpyDeviceToHost));
+    PSV_HIP(hipMemcpy(h_out.data(), out, n * sizeof(double), hipMemcpyDeviceToHost));
+    double emax = 0.0, vmax = 0.0;
+    for (size_t c = 0; c < n; ++c) {
+        emax = std::fmax(emax, std::fabs(h_out[c] - h_ref[c]));
+        vmax = std::fmax(vmax, std::fabs(h_ref[c]));
+    }
+    const double tol = fp32 ? 1e-3 : 1e-10;
+    if (!(emax <= tol * vmax)) {
+        if (std::getenv("PSV_LOG"))
+            std::fprintf(stderr, "psv autotune: %s tuned shapes failed parity (%.3e); keeping defaults\n",
+                         key.c_str(), emax / vmax);
+        p.lp = def;
+    } else if (std::getenv("PSV_LOG")) {
+        std::fprintf(stderr, "psv autotune: %s -> lbx %d lby %d tri_L %d\n", key.c_str(), p.lp.lbx,
+                     p.lp.lby, p.lp.tri_L);
+    }
+    store_cache(key, p.lp);
+    (void)hipStreamDestroy(s);
+    (void)hipFree(buf);
+}
+
+}  // namespace psv

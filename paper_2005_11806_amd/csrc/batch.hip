@@ -612,7 +612,7 @@ void batch_create(psv_batch& B, int n, const psv_grid* grids, const psv_opts& o)
         D.z = make_zargs(*pl, pl->scal + S_RHS_MEAN);
         D.kb = pl->lp.lby;
         int L = 8, P = 1;
-        tri_shape(pl->nz, L, P);
+        tri_shape(*pl, L, P);
         D.L = L;
         D.method = o.method;
         D.fp32 = B.fp32 ? 1 : 0;

@@ -76,7 +76,14 @@ struct Launch {
     int thr_x = 256;
     int thr_y = 256;
     int thr_z = 256;
+    int tri_L = 8;     // preferred rows per lane of the tridiagonal solve
 };
+
+// Launch-shape autotuning (autotune.cpp): times candidate shapes per pass on
+// synthetic data in the plan's workspace, checks the tuned solve against the
+// default shapes, and caches the choice per (arch, grid, precision, method).
+struct Plan;
+void autotune_plan(Plan& p);
 
 // Optional per-kernel timing: a pair of hipEvents around every launch on the
 // launch stream, summed per kernel name when the summary is read.

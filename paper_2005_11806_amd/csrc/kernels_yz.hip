@@ -79,7 +79,7 @@ void launch_fft_y(const Plan& p, bool fp32, bool inverse, const int* done, hipSt
 void launch_thomas(const Plan& p, bool fp32, double* mean_out, const int* done, hipStream_t s) {
     const ZArgs z = make_zargs(p, mean_out);
     int L = 8, P = 1;
-    tri_shape(p.nz, L, P);
+    tri_shape(p, L, P);
     const int nblk = tri_tiles(p);
     TraceScope ts(p, fp32 ? "thomas_z_fp32" : "thomas_z_fp64", s);
     if (fp32)

@@ -266,22 +266,27 @@ __device__ __forceinline__ void tri_tile(const ZArgs& z, c2<T>* __restrict__ spe
     }
 }
 
-// Rows per lane L and lanes per system P for a column of nz rows: short
-// chains keep the serial elimination short and give many waves; L grows only
-// when 64 lanes per system would not cover the column.
-inline void tri_shape(int nz, int& L, int& P) {
-    if (nz <= 8) {
+// Rows per lane L and lanes per system P for a column of nz rows, starting
+// from the preferred L (8 unless tuned): short chains keep the serial
+// elimination short and give many waves; L grows only when 64 lanes per
+// system would not cover the column.
+inline void tri_shape(int nz, int& L, int& P, int prefer = 8) {
+    if (nz <= 8 && prefer >= 8) {
         P = 1;
         L = 2;
         while (L < nz) L *= 2;
         return;
     }
-    for (L = 8; L <= 32; L *= 2) {
+    for (L = prefer; L <= 32; L *= 2) {
         P = 1;
         while (P * L < nz) P *= 2;
         if (P <= 64) return;
     }
+    L = 32;
+    P = 64;
 }
+
+inline void tri_shape(const Plan& p, int& L, int& P) { tri_shape(p.nz, L, P, p.lp.tri_L); }
 
 inline ZArgs make_zargs(const Plan& p, double* mean_out) {
     ZArgs z;
@@ -289,7 +294,7 @@ inline ZArgs make_zargs(const Plan& p, double* mean_out) {
     z.mx = p.mx;
     z.ny = p.ny;
     int L = 8, P = 1;
-    tri_shape(p.nz, L, P);
+    tri_shape(p, L, P);
     z.P = P;
     z.lz = p.grid.lz;
     z.nxny_lz = (double)p.nx * p.ny * p.grid.lz;
@@ -306,7 +311,7 @@ inline ZArgs make_zargs(const Plan& p, double* mean_out) {
 
 inline int tri_tiles(const Plan& p) {
     int L = 8, P = 1;
-    tri_shape(p.nz, L, P);
+    tri_shape(p, L, P);
     const int spb = 256 / P;
     return (p.mx * p.ny + spb - 1) / spb;
 }

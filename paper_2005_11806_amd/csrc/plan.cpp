@@ -217,7 +217,8 @@ void plan_init(Plan& p, const psv_grid& g, const psv_opts& o, bool alloc_ws) {
     p.t.vol = upload(vol);
     p.t.inv_vol = upload(inv_vol);
     // per-block partial sums: 2 per forward-x block, or the reductions' 1.5 * 1024
-    p.n_partials = std::max(8192, 2 * (p.ny / p.lp.lbx) * p.nz + 64);
+    // two per forward-x block at any lines-per-block (the autotuner may pick 1)
+    p.n_partials = std::max(8192, 2 * p.ny * p.nz + 64);
     PSV_HIP(hipMalloc(&p.partials, p.n_partials * sizeof(double)));
     PSV_HIP(hipMalloc(&p.scal, S_NSCAL * sizeof(double)));
     PSV_HIP(hipMalloc(&p.flags, F_NFLAG * sizeof(int)));
@@ -232,6 +233,7 @@ void plan_init(Plan& p, const psv_grid& g, const psv_opts& o, bool alloc_ws) {
         PSV_HIP(hipMalloc(&p.spec_t, nspec * sizeof(double2)));
         PSV_HIP(hipMalloc(&p.r_ws, 2 * ncell * sizeof(double)));
         p.own_ws = true;
+        if (p.opts.autotune >= 1) autotune_plan(p);
     }
 }
 

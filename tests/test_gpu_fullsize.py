@@ -1,0 +1,82 @@
+"""Full-size cases: 256x256x512 tanh-stretched (200 spheres) in FP64 and mixed
+precision, and the 256^3 forward + adjoint with finite-difference checks.
+The oracle runs at full size on the host (matrix-form DFTs); the residual is
+also recomputed on the host with the oracle's stencil."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import workloads as W
+from tests.gpu_util import dev, host, oracle_inputs, rel_max_err, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def tanh_case():
+    case = W.mixed_tanh()
+    g, f, rho, pp = oracle_inputs(case)
+    (po,), (oi,) = O.solve(f, g, rho, pp, with_relres=False)
+    r = O.assemble_method1(f, rho, pp, float(rho.min()), g)
+    return case, g, f, rho, pp, po, r
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_tanh_256x256x512(gpu, tanh_case, precision):
+    case, g, f, rho, pp, po, r = tanh_case
+    say(f"256x256x512 tanh {precision}")
+    plan = gpu.Plan(gpu.Grid.from_spec(case.grid), precision=precision, autotune=1)
+    p, info = plan.solve(dev(f), rho=dev(rho), p_prev=dev(pp), info=True)
+    ph = host(p)
+    err = rel_max_err(ph, po)
+    rr = O.relres(r, ph, g)[0]
+    say(f"  err vs oracle {err:.3e}, relres {info.relres:.3e} (host {rr:.3e}), steps {info.refine_steps}")
+    if precision == "fp64":
+        assert info.relres <= 1e-12 and rr <= 1e-12
+        assert err <= 1e-10
+    else:
+        assert info.relres <= 1e-10 and rr <= 1e-10
+        assert err <= 1e-7
+
+
+@pytest.mark.parametrize("precision,h_rho,tol_fd", [("fp64", 1e-5, 1e-6), ("mixed", 1e-3, 1e-4)])
+def test_grad_256cubed(gpu, precision, h_rho, tol_fd):
+    """Loss sum(w p) on the 256^3 two-phase setup: adjoint vs the oracle's
+    adjoint, and 16 central-difference directions (8 in f, 8 in rho)."""
+    case = W.grad256()
+    g, f, rho, pp = oracle_inputs(case)
+    w = case.w
+    rho0 = float(rho.min())
+    say(f"grad256 {precision}")
+    plan = gpu.Plan(gpu.Grid.from_spec(case.grid), precision=precision, autotune=1)
+    F, R, P, Wd = dev(f), dev(rho), dev(pp), dev(w)
+    gr = plan.adjoint(Wd, f=F, rho=R, p_prev=P, rho0=rho0, grad_rho0=True)
+    if precision == "fp64":
+        ref = O.adjoint_step(w, f, rho, rho0, pp, g)
+        ef = rel_max_err(host(gr["f"]), ref.grad_f)
+        er = rel_max_err(host(gr["rho"]), ref.grad_rho)
+        say(f"  vs oracle: grad_f {ef:.2e} grad_rho {er:.2e} grad_rho0 "
+            f"{abs(gr['rho0'] - ref.grad_rho0) / abs(ref.grad_rho0):.2e}")
+        assert ef <= 1e-10 and er <= 1e-9
+        assert abs(gr["rho0"] - ref.grad_rho0) <= 1e-9 * abs(ref.grad_rho0)
+
+    def loss(ff, rr):
+        return float((Wd * plan.solve(ff, rho=rr, p_prev=P, rho0=rho0)).sum())
+
+    worst = 0.0
+    for d in range(16):
+        # direction d: stream 6 of the grad256 seeds, one generator per direction
+        v = dev(np.random.default_rng([W.SEED_ROOT, 4, 0, W.STREAM_FD, d]).standard_normal(f.shape))
+        if d < 8:
+            h = 1e-2
+            fd = (loss(F + h * v, R) - loss(F - h * v, R)) / (2 * h)
+            an = float((gr["f"] * v).sum())
+        else:
+            vr = R * v
+            fd = (loss(F, R + h_rho * vr) - loss(F, R - h_rho * vr)) / (2 * h_rho)
+            an = float((gr["rho"] * vr).sum())
+        rel = abs(fd - an) / max(abs(an), 1e-300)
+        worst = max(worst, rel)
+        assert rel <= tol_fd, (d, fd, an)
+    say(f"  worst FD relative difference over 16 directions {worst:.2e}")
