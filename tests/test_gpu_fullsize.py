@@ -40,10 +40,14 @@ def test_tanh_256x256x512(gpu, tanh_case, precision):
         assert err <= 1e-7
 
 
-@pytest.mark.parametrize("precision,h_rho,tol_fd", [("fp64", 1e-5, 1e-6), ("mixed", 1e-3, 1e-4)])
+@pytest.mark.parametrize("precision,h_rho,tol_fd", [("fp64", 1e-4, 1e-5), ("mixed", 1e-3, 1e-4)])
 def test_grad_256cubed(gpu, precision, h_rho, tol_fd):
     """Loss sum(w p) on the 256^3 two-phase setup: adjoint vs the oracle's
-    adjoint, and 16 central-difference directions (8 in f, 8 in rho)."""
+    adjoint, and 16 central-difference directions (8 in f, 8 in rho).
+    The loss is affine in f (central differences exact up to rounding); in rho
+    the error is ~ eps_solve |L| / h + h^2 |L'''| / 6, hence the relative step
+    h = 1e-4 and the 1e-5 gate in FP64 (1e-3 and 1e-4 in mixed precision,
+    whose solves are accurate to relres 1e-10)."""
     case = W.grad256()
     g, f, rho, pp = oracle_inputs(case)
     w = case.w
