@@ -17,6 +17,7 @@
 #include <string>
 #include <vector>
 
+#include "pass_x.hpp"
 #include "pass_yz.hpp"
 
 namespace psv {
@@ -98,8 +99,7 @@ void solve_once(const Plan& p, const FwdArgs& a, double* out, hipStream_t s) {
 
 bool fits_x(const Plan& p, int lb) {
     if (p.ny % lb) return false;
-    const size_t bytes = ((size_t)lb * (p.nx + 1) + p.nx) * sizeof(double2);
-    return bytes <= 62 * 1024;
+    return x_lds_max(p.nx, lb) <= 62 * 1024;
 }
 
 bool fits_y(const Plan& p, int kb) {

@@ -235,16 +235,17 @@ __device__ __forceinline__ void run_y(const ProblemDesc& D, int b, unsigned char
 }
 
 template <typename T>
-__device__ __forceinline__ void run_z(const ProblemDesc& D, double* mean_out, int b) {
+__device__ __forceinline__ void run_z(const ProblemDesc& D, double* mean_out, int b,
+                                      unsigned char* smem) {
     ZArgs z = D.z;
     z.rhs_mean = mean_out;
     c2<T>* sp = reinterpret_cast<c2<T>*>(D.spec_t);
     switch (D.L) {
-        case 2: tri_tile<T, 2>(z, sp, b); return;
-        case 4: tri_tile<T, 4>(z, sp, b); return;
-        case 8: tri_tile<T, 8>(z, sp, b); return;
-        case 16: tri_tile<T, 16>(z, sp, b); return;
-        default: tri_tile<T, 32>(z, sp, b); return;
+        case 2: tri_tile<T, 2>(z, sp, b, smem); return;
+        case 4: tri_tile<T, 4>(z, sp, b, smem); return;
+        case 8: tri_tile<T, 8>(z, sp, b, smem); return;
+        case 16: tri_tile<T, 16>(z, sp, b, smem); return;
+        default: tri_tile<T, 32>(z, sp, b, smem); return;
     }
 }
 
@@ -281,9 +282,9 @@ __device__ __forceinline__ void run_task(const ProblemDesc& D, const ProblemIO& 
     } else if constexpr (KIND == K_YI) {
         run_y<T, +1>(D, b, smem);
     } else if constexpr (KIND == K_Z) {
-        run_z<T>(D, D.scal + (D.fp32 ? S_MEAN2 : S_RHS_MEAN), b);
+        run_z<T>(D, D.scal + (D.fp32 ? S_MEAN2 : S_RHS_MEAN), b, smem);
     } else if constexpr (KIND == K_Z2) {
-        run_z<T>(D, D.scal + S_MEAN2, b);
+        run_z<T>(D, D.scal + S_MEAN2, b, smem);
     } else if constexpr (KIND == K_INV) {
         run_inv<T, INV_STORE>(D, io.pout, b, smem);
     } else if constexpr (KIND == K_INVADD) {
@@ -457,6 +458,11 @@ static size_t kind_lds(const Plan& p, int kind, bool fp32) {
         case K_FWD: case K_RES: return fwd_x_lds(g, cs);
         case K_INV: case K_INVADD: return inv_x_lds(g, cs);
         case K_Y: case K_YI: return fft_y_lds(p.ny, p.lp.lby, cs);
+        case K_Z: case K_Z2: {
+            int L = 8, P = 1;
+            tri_shape(p, L, P);
+            return fp32 ? tri_lds<float>(L) : tri_lds<double>(L);
+        }
         default: return 0;
     }
 }

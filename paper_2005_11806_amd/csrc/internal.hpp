@@ -7,7 +7,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/psv.h"
+#include "psv.h"
 #include "device_common.hpp"
 
 namespace psv {

@@ -18,9 +18,29 @@ __global__ void __launch_bounds__(RB) k_min_partial(const double* __restrict__ x
     __shared__ int si[RB];
     double best = __builtin_inf();
     int bi = 0x7fffffff;
-    for (size_t c = (size_t)blockIdx.x * RB + threadIdx.x; c < n; c += (size_t)gridDim.x * RB) {
-        const double v = x[c];
-        if (v < best) { best = v; bi = (int)c; }
+    // pairs (16-byte loads), four in flight, visited in increasing index
+    // order so that a strict '<' keeps the first minimum
+    const double2* x2 = reinterpret_cast<const double2*>(x);
+    const size_t n2 = n / 2, stride = (size_t)gridDim.x * RB;
+    size_t c = (size_t)blockIdx.x * RB + threadIdx.x;
+    for (; c + 3 * stride < n2; c += 4 * stride) {
+        double2 v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = x2[c + u * stride];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (v[u].x < best) { best = v[u].x; bi = (int)(2 * (c + u * stride)); }
+            if (v[u].y < best) { best = v[u].y; bi = (int)(2 * (c + u * stride) + 1); }
+        }
+    }
+    for (; c < n2; c += stride) {
+        const double2 v = x2[c];
+        if (v.x < best) { best = v.x; bi = (int)(2 * c); }
+        if (v.y < best) { best = v.y; bi = (int)(2 * c + 1); }
+    }
+    if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0 && x[n - 1] < best) {
+        best = x[n - 1];
+        bi = (int)(n - 1);
     }
     sv[threadIdx.x] = best;
     si[threadIdx.x] = bi;

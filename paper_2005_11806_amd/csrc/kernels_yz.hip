@@ -16,8 +16,9 @@ __global__ void __launch_bounds__(256) k_fft_y_t(int ny_rt, int nz, int mx, int 
 
 template <typename T, int L>
 __global__ void __launch_bounds__(256) k_tri_wave(ZArgs z, c2<T>* __restrict__ spec, const int* done) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     if (done && *done) return;
-    tri_tile<T, L>(z, spec, blockIdx.x);
+    tri_tile<T, L>(z, spec, blockIdx.x, smem_raw);
 }
 
 // y-line lengths with a compile-time FFT; others use the runtime one
@@ -45,12 +46,13 @@ void fft_y_dispatch(const Plan& p, int nblk, int kb, const c2<T>* in, c2<T>* out
 template <typename T>
 void tri_launch(const ZArgs& z, int L, int nblk, void* spec, const int* done, hipStream_t s) {
     c2<T>* sp = reinterpret_cast<c2<T>*>(spec);
+    const size_t lds = tri_lds<T>(L);
     switch (L) {
-        case 2: hipLaunchKernelGGL((k_tri_wave<T, 2>), dim3(nblk), dim3(256), 0, s, z, sp, done); break;
-        case 4: hipLaunchKernelGGL((k_tri_wave<T, 4>), dim3(nblk), dim3(256), 0, s, z, sp, done); break;
-        case 8: hipLaunchKernelGGL((k_tri_wave<T, 8>), dim3(nblk), dim3(256), 0, s, z, sp, done); break;
-        case 16: hipLaunchKernelGGL((k_tri_wave<T, 16>), dim3(nblk), dim3(256), 0, s, z, sp, done); break;
-        default: hipLaunchKernelGGL((k_tri_wave<T, 32>), dim3(nblk), dim3(256), 0, s, z, sp, done); break;
+        case 2: hipLaunchKernelGGL((k_tri_wave<T, 2>), dim3(nblk), dim3(256), lds, s, z, sp, done); break;
+        case 4: hipLaunchKernelGGL((k_tri_wave<T, 4>), dim3(nblk), dim3(256), lds, s, z, sp, done); break;
+        case 8: hipLaunchKernelGGL((k_tri_wave<T, 8>), dim3(nblk), dim3(256), lds, s, z, sp, done); break;
+        case 16: hipLaunchKernelGGL((k_tri_wave<T, 16>), dim3(nblk), dim3(256), lds, s, z, sp, done); break;
+        default: hipLaunchKernelGGL((k_tri_wave<T, 32>), dim3(nblk), dim3(256), lds, s, z, sp, done); break;
     }
 }
 

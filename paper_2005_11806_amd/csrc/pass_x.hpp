@@ -25,10 +25,39 @@ struct Stencil {
     const double* vol;
 };
 
-// LDS bytes of the x tiles for complex element size csz
-inline size_t fwd_x_lds(const XGeom& g, size_t csz) { return ((size_t)2 * g.lb * g.M + 2 * g.M) * csz; }
-inline size_t inv_x_lds(const XGeom& g, size_t csz) {
-    return ((size_t)g.lb * (2 * g.M + 1) + 2 * g.M) * csz;
+// LDS bytes of the x tiles for complex element size csz. Forward: FFT buffer,
+// twiddles, then either the second FFT buffer or the staged rows of p and rho
+// (lb + 2 rows each, FP64), which the second buffer reuses after assembly.
+inline size_t fwd_x_lds_n(int nx, int lb, size_t csz) {
+    const size_t M = nx / 2;
+    const size_t stage = (size_t)2 * (lb + 2) * nx * sizeof(double);
+    const size_t buf = (size_t)lb * M * csz;
+    return buf + 2 * M * csz + 16 + (stage > buf ? stage : buf);
+}
+inline size_t inv_x_lds_n(int nx, int lb, size_t csz) {
+    const size_t M = nx / 2;
+    return ((size_t)lb * (2 * M + 1) + 2 * M) * csz;
+}
+inline size_t fwd_x_lds(const XGeom& g, size_t csz) { return fwd_x_lds_n(g.nx, g.lb, csz); }
+inline size_t inv_x_lds(const XGeom& g, size_t csz) { return inv_x_lds_n(g.nx, g.lb, csz); }
+// the larger of the two at FP64, for choosing lines per block
+inline size_t x_lds_max(int nx, int lb) {
+    const size_t a = fwd_x_lds_n(nx, lb, 16), b = inv_x_lds_n(nx, lb, 16);
+    return a > b ? a : b;
+}
+
+// 1/s from the hardware estimate and two Newton steps
+__device__ __forceinline__ double rcp_nr(double s) {
+    double r = __builtin_amdgcn_rcp(s);
+    r = fma(r, fma(-s, r, 1.0), r);
+    return fma(r, fma(-s, r, 1.0), r);
+}
+
+// (1 - rho0/rho_f) (p_R - p_L) across the face between cells L and R, with
+// rho_f = (rho_L + rho_R)/2, i.e. (s - 2 rho0)/s with s = rho_L + rho_R.
+__device__ __forceinline__ double bflux(double rl, double rr, double pl, double pr, double two_r0) {
+    const double s = rl + rr;
+    return (s - two_r0) * rcp_nr(s) * (pr - pl);
 }
 
 // Blocks are dispatched round-robin over the 8 XCDs; remap so that each XCD
@@ -38,57 +67,6 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
     const int q = nb >> 3, r = nb & 7;
     const int x = b & 7, i = b >> 3;
     return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + i;
-}
-
-// Method-I right-hand side at one cell (Eq. poisson_me1):
-//   rho0 f + sum over faces of (1 - rho0/rho_f) (grad p)_f, differenced,
-// with beta_f = 1 - 2 rho0 / (rho_L + rho_R); wall faces carry no flux.
-__device__ __forceinline__ double method1_cell(const double* __restrict__ f,
-                                               const double* __restrict__ rho,
-                                               const double* __restrict__ pp, double rho0,
-                                               int i, int j, int k, const XGeom& g,
-                                               const Stencil& st) {
-    const size_t plane = (size_t)g.nx * g.ny;
-    const size_t row = (size_t)k * plane + (size_t)j * g.nx;
-    const size_t c = row + i;
-    const int ie = (i + 1 == g.nx) ? 0 : i + 1;
-    const int iw = (i == 0) ? g.nx - 1 : i - 1;
-    const int jn = (j + 1 == g.ny) ? 0 : j + 1;
-    const int js = (j == 0) ? g.ny - 1 : j - 1;
-    const double pc = pp[c], rc = rho[c];
-    const double two_r0 = 2.0 * rho0;
-    double acc;
-    {
-        const double pe = pp[row + ie], pw = pp[row + iw];
-        const double re = rho[row + ie], rw = rho[row + iw];
-        const double fe = (re + rc - two_r0) / (re + rc) * (pe - pc);
-        const double fw = (rw + rc - two_r0) / (rw + rc) * (pc - pw);
-        acc = (fe - fw) * (g.inv_dx * g.inv_dx);
-    }
-    {
-        const size_t cn = (size_t)k * plane + (size_t)jn * g.nx + i;
-        const size_t cs = (size_t)k * plane + (size_t)js * g.nx + i;
-        const double pn = pp[cn], ps = pp[cs];
-        const double rn = rho[cn], rs = rho[cs];
-        const double fn = (rn + rc - two_r0) / (rn + rc) * (pn - pc);
-        const double fs = (rs + rc - two_r0) / (rs + rc) * (pc - ps);
-        acc += (fn - fs) * (g.inv_dy * g.inv_dy);
-    }
-    {
-        double ft = 0.0, fb = 0.0;
-        if (k + 1 < g.nz) {
-            const size_t ct = c + plane;
-            const double rt = rho[ct];
-            ft = (rt + rc - two_r0) / (rt + rc) * (pp[ct] - pc) * st.inv_g[k + 1];
-        }
-        if (k > 0) {
-            const size_t cb = c - plane;
-            const double rb = rho[cb];
-            fb = (rb + rc - two_r0) / (rb + rc) * (pc - pp[cb]) * st.inv_g[k];
-        }
-        acc += (ft - fb) * st.inv_h[k];
-    }
-    return acc + rho0 * f[c];
 }
 
 // 7-point L p at one cell (flux form in z; zero wall flux).
@@ -122,36 +100,103 @@ __device__ __forceinline__ void fwd_x_tile(const XGeom& g, const Stencil& st, co
     const int k = b / g.tiles;
     const int j0 = (b - k * g.tiles) * g.lb;
     const int M = N ? N : g.M;
+    const int nx = 2 * M;
+    const int lb = g.lb;
     C* buf0 = reinterpret_cast<C*>(smem);
-    C* buf1 = buf0 + g.lb * M;
-    C* tw = buf1 + g.lb * M;  // exp(-2 pi i t / nx), t < nx
+    C* tw = buf0 + lb * M;  // exp(-2 pi i t / nx), t < nx
+    // staging area, 16-byte aligned (FP32 buffers may end on an 8-byte boundary)
+    const size_t off = ((reinterpret_cast<size_t>(tw + 2 * M) - reinterpret_cast<size_t>(smem)) + 15) & ~size_t(15);
+    unsigned char* rest = smem + off;
+    C* buf1 = reinterpret_cast<C*>(rest);       // second FFT buffer, used after assembly
+    double2* pt = reinterpret_cast<double2*>(rest);  // staged p rows j0-1 .. j0+lb (periodic)
+    double2* rt = pt + (lb + 2) * M;                 // staged rho rows (Method I)
     for (int t = threadIdx.x; t < 2 * M; t += 256) tw[t] = tw_g[t];
-    TC* rbuf = reinterpret_cast<TC*>(buf0);
+    const size_t plane = (size_t)nx * g.ny;
+    if (MODE != FWD_CONST) {
+        const double2* p2 = reinterpret_cast<const double2*>(a.pprev);
+        const double2* r2g = reinterpret_cast<const double2*>(a.rho);
+        for (int t = threadIdx.x; t < (lb + 2) * M; t += 256) {
+            const int rr = t / M;
+            const int q = t - rr * M;
+            int j = j0 - 1 + rr;
+            j = (j < 0) ? j + g.ny : (j >= g.ny ? j - g.ny : j);
+            const size_t src = ((size_t)k * g.ny + j) * M + q;
+            pt[t] = p2[src];
+            if (MODE == FWD_METHOD1) rt[t] = r2g[src];
+        }
+        __syncthreads();
+    }
 
     const double rho0 = (MODE == FWD_METHOD1) ? *a.rho0 : 0.0;
+    const double two_r0 = 2.0 * rho0;
     const double mean = (MODE == FWD_RESID) ? *a.mean : 0.0;
     const double sc = (MODE == FWD_CONST && a.scale) ? a.scale[k] : 1.0;
+    const double idx2 = g.inv_dx * g.inv_dx, idy2 = g.inv_dy * g.inv_dy;
+    const bool has_t = k + 1 < g.nz, has_b = k > 0;
+    const double igt = has_t ? st.inv_g[k + 1] : 0.0, igb = has_b ? st.inv_g[k] : 0.0;
+    const double ih = st.inv_h[k];
     double res2 = 0.0, r2 = 0.0, rsum = 0.0;
-    const int ncell = g.lb * g.nx;
-    for (int t = threadIdx.x; t < ncell; t += 256) {
-        const int line = t / g.nx;
-        const int i = t - line * g.nx;
-        const int j = j0 + line;
-        const size_t c = ((size_t)k * g.ny + j) * g.nx + i;
-        double r;
+    // one thread per pair of cells (2n, 2n+1): exactly the packed input
+    // z_n = r_{2n} + i r_{2n+1} of the half-length transform
+    for (int t = threadIdx.x; t < lb * M; t += 256) {
+        const int line = t / M;
+        const int n = t - line * M;
+        const size_t c2 = (((size_t)k * g.ny + j0 + line) * nx) / 2 + n;  // double2 index
+        double v0, v1;
         if (MODE == FWD_CONST) {
-            r = a.f[c] * sc;
-        } else if (MODE == FWD_METHOD1) {
-            r = method1_cell(a.f, a.rho, a.pprev, rho0, i, j, k, g, st);
+            const double2 fv = reinterpret_cast<const double2*>(a.f)[c2];
+            v0 = fv.x * sc;
+            v1 = fv.y * sc;
         } else {
-            const double rp = a.r_in[c] - mean;
-            r = rp - lap_cell(a.pprev, i, j, k, g, st);
-            res2 += r * r;
-            r2 += rp * rp;
+            const double2* P = pt + (line + 1) * M;
+            const double2 pc = P[n], pn = P[n + M], ps = P[n - M];
+            const double pw = P[n == 0 ? M - 1 : n - 1].y, pe = P[n + 1 == M ? 0 : n + 1].x;
+            double2 ptz{0.0, 0.0}, pbz{0.0, 0.0};
+            const double2* pg = reinterpret_cast<const double2*>(a.pprev);
+            if (has_t) ptz = pg[c2 + plane / 2];
+            if (has_b) pbz = pg[c2 - plane / 2];
+            if (MODE == FWD_METHOD1) {
+                const double2* R = rt + (line + 1) * M;
+                const double2 rc = R[n], rn = R[n + M], rs = R[n - M];
+                const double rw = R[n == 0 ? M - 1 : n - 1].y, re = R[n + 1 == M ? 0 : n + 1].x;
+                const double2* rg = reinterpret_cast<const double2*>(a.rho);
+                double2 rtz{1.0, 1.0}, rbz{1.0, 1.0};
+                if (has_t) rtz = rg[c2 + plane / 2];
+                if (has_b) rbz = rg[c2 - plane / 2];
+                const double2 fv = reinterpret_cast<const double2*>(a.f)[c2];
+                // x faces: west of 2n, between the pair, east of 2n+1
+                const double fw = bflux(rw, rc.x, pw, pc.x, two_r0);
+                const double fm = bflux(rc.x, rc.y, pc.x, pc.y, two_r0);
+                const double fe = bflux(rc.y, re, pc.y, pe, two_r0);
+                double d0 = (fm - fw) * idx2, d1 = (fe - fm) * idx2;
+                d0 += (bflux(rc.x, rn.x, pc.x, pn.x, two_r0) - bflux(rs.x, rc.x, ps.x, pc.x, two_r0)) * idy2;
+                d1 += (bflux(rc.y, rn.y, pc.y, pn.y, two_r0) - bflux(rs.y, rc.y, ps.y, pc.y, two_r0)) * idy2;
+                const double t0 = has_t ? bflux(rc.x, rtz.x, pc.x, ptz.x, two_r0) * igt : 0.0;
+                const double t1 = has_t ? bflux(rc.y, rtz.y, pc.y, ptz.y, two_r0) * igt : 0.0;
+                const double b0 = has_b ? bflux(rbz.x, rc.x, pbz.x, pc.x, two_r0) * igb : 0.0;
+                const double b1 = has_b ? bflux(rbz.y, rc.y, pbz.y, pc.y, two_r0) * igb : 0.0;
+                d0 += (t0 - b0) * ih;
+                d1 += (t1 - b1) * ih;
+                v0 = d0 + rho0 * fv.x;
+                v1 = d1 + rho0 * fv.y;
+            } else {  // residual r - mean - L p
+                const double2 rin = reinterpret_cast<const double2*>(a.r_in)[c2];
+                double l0 = ((pc.y - pc.x) - (pc.x - pw)) * idx2;
+                double l1 = ((pe - pc.y) - (pc.y - pc.x)) * idx2;
+                l0 += ((pn.x - pc.x) - (pc.x - ps.x)) * idy2;
+                l1 += ((pn.y - pc.y) - (pc.y - ps.y)) * idy2;
+                l0 += ((has_t ? (ptz.x - pc.x) * igt : 0.0) - (has_b ? (pc.x - pbz.x) * igb : 0.0)) * ih;
+                l1 += ((has_t ? (ptz.y - pc.y) * igt : 0.0) - (has_b ? (pc.y - pbz.y) * igb : 0.0)) * ih;
+                const double rp0 = rin.x - mean, rp1 = rin.y - mean;
+                v0 = rp0 - l0;
+                v1 = rp1 - l1;
+                res2 += v0 * v0 + v1 * v1;
+                r2 += rp0 * rp0 + rp1 * rp1;
+            }
         }
-        if (a.r_out) a.r_out[c] = r;
-        rsum += r;
-        rbuf[line * g.nx + i] = (TC)r;  // z_n = r_{2n} + i r_{2n+1}
+        if (a.r_out) reinterpret_cast<double2*>(a.r_out)[c2] = double2{v0, v1};
+        rsum += v0 + v1;
+        buf0[line * M + n] = C{(TC)v0, (TC)v1};
     }
     if (MODE != FWD_RESID && a.partials) {
         // FP64 volume-weighted sum of the right-hand side (its mean is the
@@ -229,17 +274,21 @@ __device__ __forceinline__ void inv_x_tile(const XGeom& g, const c2<TC>* __restr
     __syncthreads();
     C* z = lds_fft_n<N, +1, 2>(buf0, xb, M, g.lb, M, g.rad, tw);
     const double s = (MODE == INV_SCALE) ? scale * vol[k] : scale;
-    const int ncell = g.lb * g.nx;
-    for (int t = threadIdx.x; t < ncell; t += 256) {
-        const int line = t / g.nx;
-        const int i = t - line * g.nx;
-        const C v = z[line * M + (i >> 1)];
-        const double x = (double)((i & 1) ? v.y : v.x) * s;
-        const size_t c = ((size_t)k * g.ny + j0 + line) * g.nx + i;
-        if (MODE == INV_ADD)
-            out[c] += x;
-        else
-            out[c] = x;
+    // z_n = x_{2n} + i x_{2n+1}: one 16-byte store per pair of cells
+    double2* out2 = reinterpret_cast<double2*>(out);
+    const int npair = g.lb * M;
+    for (int t = threadIdx.x; t < npair; t += 256) {
+        const int line = t / M;
+        const int n = t - line * M;
+        const C v = z[t];
+        const size_t c2 = (((size_t)k * g.ny + j0 + line) * (2 * M)) / 2 + n;
+        double2 x{(double)v.x * s, (double)v.y * s};
+        if (MODE == INV_ADD) {
+            const double2 o = out2[c2];
+            x.x += o.x;
+            x.y += o.y;
+        }
+        out2[c2] = x;
     }
 }
 

@@ -72,6 +72,7 @@ __device__ __forceinline__ void fft_y_tile(int ny_rt, int nz, int mx, int kb, co
 struct ZArgs {
     int nz, mx, ny;
     int P;           // lanes per system (power of 2, <= 64)
+    float rcp_nz;    // 1/nz, for splitting staged element indices
     double nxny_lz;  // nx * ny * lz
     double lz;
     const double* za;
@@ -146,11 +147,21 @@ __device__ __forceinline__ void zero_mode_wave(const ZArgs& z, c2<TS>* colg) {
 __device__ __forceinline__ double shfl_v(double v, int src) { return __shfl(v, src, 64); }
 __device__ __forceinline__ float shfl_v(float v, int src) { return __shfl(v, src, 64); }
 
-// Tridiagonal tile b: systems [b * 256/P, (b+1) * 256/P). Tile 0's first wave
-// also solves the (0,0) column.
+// LDS of a tridiagonal tile: columns staged with one pad entry per partition
+// (rows per lane L <= 8; longer chains read their rows from global memory)
+template <typename T>
+inline size_t tri_lds(int L) { return L <= 8 ? (size_t)256 * (L + 1) * sizeof(c2<T>) : 0; }
+
+// Tridiagonal tile b: systems [b * 256/P, (b+1) * 256/P), whose columns are
+// contiguous in layout B. For L <= 8 the block copies them to LDS with
+// coalesced 16-byte loads (partition p of a system at offset p (L+1)), each
+// lane then takes its L rows from there, and the solved columns go back the
+// same way. Tile 0's first wave also solves the (0,0) column.
 template <typename T, int L>
-__device__ __forceinline__ void tri_tile(const ZArgs& z, c2<T>* __restrict__ spec, int b) {
+__device__ __forceinline__ void tri_tile(const ZArgs& z, c2<T>* __restrict__ spec, int b,
+                                         unsigned char* smem) {
     using C = c2<T>;
+    constexpr bool STAGE = L <= 8;
     const int S = z.mx * z.ny;
     if (b == 0 && threadIdx.x < 64) zero_mode_wave<T>(z, spec);
     const int P = z.P;
@@ -158,16 +169,38 @@ __device__ __forceinline__ void tri_tile(const ZArgs& z, c2<T>* __restrict__ spe
     const int p = lane & (P - 1);
     const int gbase = lane - p;  // first lane of this system's group
     const int sys_per_block = 256 / P;
-    const int s = b * sys_per_block + (int)(threadIdx.x / P);
+    const int s0 = b * sys_per_block;
+    const int sl = (int)(threadIdx.x / P);  // system within the tile
+    const int s = s0 + sl;
     const bool active = (s < S) && (s != 0);
     const int k0 = p * L;
     C* colp = spec + (size_t)(active ? s : 0) * z.nz;
+    C* lds = reinterpret_cast<C*>(smem);
+    const int sstride = P * (L + 1);
+    const int cnt = min(sys_per_block, S - s0) * z.nz;
     C d[L];
     T aa[L], cc[L];
+    if constexpr (STAGE) {
+        const C* src = spec + (size_t)s0 * z.nz;
+        for (int e = threadIdx.x; e < cnt; e += 256) {
+            // (system, row) of element e; the float estimate is off by at most one
+            int q = (int)((float)e * z.rcp_nz);
+            int r = e - q * z.nz;
+            if (r < 0) { --q; r += z.nz; } else if (r >= z.nz) { ++q; r -= z.nz; }
+            lds[q * sstride + (r / L) * (L + 1) + (r % L)] = src[e];
+        }
+        __syncthreads();
 #pragma unroll
-    for (int i = 0; i < L; ++i) {
-        const int k = k0 + i;
-        d[i] = (active && k < z.nz) ? colp[k] : C{(T)0, (T)0};
+        for (int i = 0; i < L; ++i) {
+            const int k = k0 + i;
+            d[i] = (active && k < z.nz) ? lds[sl * sstride + p * (L + 1) + i] : C{(T)0, (T)0};
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < L; ++i) {
+            const int k = k0 + i;
+            d[i] = (active && k < z.nz) ? colp[k] : C{(T)0, (T)0};
+        }
     }
     double lam = 0.0;
     if (active) {
@@ -257,7 +290,23 @@ __device__ __forceinline__ void tri_tile(const ZArgs& z, c2<T>* __restrict__ spe
         d[i] = C{d[i].x - aa[i] * xf.x - cc[i] * xl.x, d[i].y - aa[i] * xf.y - cc[i] * xl.y};
     d[0] = xf;
     d[L - 1] = xl;
-    if (active) {
+    if constexpr (STAGE) {
+        // each lane rewrites only the slots it read; then the block stores the
+        // tile coalesced, leaving the (0,0) column to the zero-mode wave
+        if (active) {
+#pragma unroll
+            for (int i = 0; i < L; ++i)
+                if (k0 + i < z.nz) lds[sl * sstride + p * (L + 1) + i] = d[i];
+        }
+        __syncthreads();
+        C* dst = spec + (size_t)s0 * z.nz;
+        for (int e = threadIdx.x; e < cnt; e += 256) {
+            int q = (int)((float)e * z.rcp_nz);
+            int r = e - q * z.nz;
+            if (r < 0) { --q; r += z.nz; } else if (r >= z.nz) { ++q; r -= z.nz; }
+            if (s0 + q != 0) dst[e] = lds[q * sstride + (r / L) * (L + 1) + (r % L)];
+        }
+    } else if (active) {
 #pragma unroll
         for (int i = 0; i < L; ++i) {
             const int k = k0 + i;
@@ -296,6 +345,7 @@ inline ZArgs make_zargs(const Plan& p, double* mean_out) {
     int L = 8, P = 1;
     tri_shape(p, L, P);
     z.P = P;
+    z.rcp_nz = 1.0f / (float)p.nz;
     z.lz = p.grid.lz;
     z.nxny_lz = (double)p.nx * p.ny * p.grid.lz;
     z.za = p.t.za;

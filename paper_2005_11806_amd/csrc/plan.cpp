@@ -6,7 +6,7 @@
 #include <cstring>
 #include <sstream>
 
-#include "internal.hpp"
+#include "pass_x.hpp"
 
 namespace psv {
 
@@ -193,12 +193,12 @@ void plan_init(Plan& p, const psv_grid& g, const psv_opts& o, bool alloc_ws) {
     PSV_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, p.device));
     const size_t budget = (size_t)std::min(lds_max, 64 * 1024) - 2048;
     // (the twiddle table of each direction also lives in LDS)
-    const size_t bx = budget - (size_t)p.nx * sizeof(double2);
     const size_t by = budget - (size_t)p.ny * sizeof(double2);
-    p.lp.lbx = pick_lines(p.ny, (size_t)(p.nx + 1) * sizeof(double2), bx, 16);
+    p.lp.lbx = 1;
+    while (p.lp.lbx * 2 <= 16 && p.ny % (p.lp.lbx * 2) == 0 && x_lds_max(p.nx, p.lp.lbx * 2) <= budget)
+        p.lp.lbx *= 2;
     p.lp.lby = pick_lines(1 << 20, (size_t)2 * (p.ny + 1) * sizeof(double2), by, 16);
-    if ((size_t)p.lp.lbx * (p.nx + 1) * sizeof(double2) > bx ||
-        (size_t)p.lp.lby * 2 * (p.ny + 1) * sizeof(double2) > by)
+    if (x_lds_max(p.nx, p.lp.lbx) > budget || (size_t)p.lp.lby * 2 * (p.ny + 1) * sizeof(double2) > by)
         fail(PSV_ERR_UNSUPPORTED_SIZE, "line length exceeds the LDS budget");
 
     p.t.twx64 = upload(tx64);
