@@ -58,9 +58,12 @@ def make_case(name):
     raise ValueError(name)
 
 
-def kernel_bytes(name, nx, ny, nz):
+def kernel_bytes(name, nx, ny, nz, kc=None):
     """Algorithmic HBM bytes of one launch: what the pass must read and write
-    at least (inputs once, outputs once; spectrum = (nx/2+1) ny nz complex)."""
+    at least (inputs once, outputs once; spectrum = (nx/2+1) ny nz complex;
+    kc = rows per chunk of the z partition, whose 2 ceil(nz/kc) interface rows
+    per wavenumber pair the interface pass reads with their three real
+    factors and writes back)."""
     n = nx * ny * nz
     ns = (nx // 2 + 1) * ny * nz
     c = 8 if name.endswith("fp32") else 16  # bytes per complex spectrum element
@@ -70,8 +73,13 @@ def kernel_bytes(name, nx, ny, nz):
         return 2 * 8 * n + c * ns
     if name.startswith("fwd_x_const"):
         return 8 * n + c * ns
-    if name.startswith(("fft_y", "thomas_z")):
+    if name.startswith("yz_"):
         return 2 * c * ns
+    if name.startswith("z_interface"):
+        if kc is None:
+            return None
+        rows = 2 * -(-nz // kc) * (nx // 2 + 1) * ny
+        return rows * (2 * c + 3 * c // 2)
     if name.startswith("inv_x_add"):
         return c * ns + 2 * 8 * n
     if name.startswith("inv_x"):
@@ -81,6 +89,15 @@ def kernel_bytes(name, nx, ny, nz):
     if name == "residual_fp64":
         return 2 * 8 * n
     return None
+
+
+def kernel_row(name, rec, spec, kc):
+    """Launch count, average duration and algorithmic GB/s of one kernel."""
+    launches, total_ms = rec
+    avg_us = 1e3 * total_ms / launches
+    b = kernel_bytes(name, spec.nx, spec.ny, spec.nz, kc)
+    return {"launches": launches, "avg_us": avg_us,
+            "alg_gbs": (b / (avg_us * 1e-6) / 1e9) if b else None}
 
 
 def source_digest():
@@ -121,11 +138,11 @@ def trace_name(rocprof_name):
     if "k_inv_x<" in n:
         mode = n.split("k_inv_x<")[1].split(",")[2].strip()
         return f"inv_x_{['store', 'add', 'scale'][int(mode)]}_{prec}"
-    if "k_fft_y_t<" in n:
-        d = n.split("k_fft_y_t<")[1].split(",")[2].strip()
-        return f"fft_y_{'fwd' if d.startswith('-') else 'inv'}_{prec}"
-    if "k_tri_wave<" in n:
-        return f"thomas_z_{prec}"
+    if "k_yz<" in n:
+        inv = n.split("k_yz<")[1].split(",")[2].split(">")[0].strip()
+        return f"yz_{'inv' if inv == 'true' else 'fwd'}_{prec}"
+    if "k_ifc<" in n:
+        return f"z_interface_{prec}"
     if "k_min_partial" in n or "k_min_final" in n:
         return "min_rho"
     if "k_residual" in n:
@@ -381,13 +398,15 @@ def main():
     dom = max(summary, key=lambda k: summary[k][1])
     launches, total_ms = summary[dom]
     avg_s = total_ms / launches * 1e-3
-    alg = kernel_bytes(dom, spec.nx, spec.ny, spec.nz)
+    kc = plan.launch_shape()[1]
+    alg = kernel_bytes(dom, spec.nx, spec.ny, spec.nz, kc)
     achieved = alg / avg_s / 1e9 if alg else None
     traffic = measured_traffic(dom, args.workload)
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": traffic,
                 "kernel": dom, "avg_launch_us": avg_s * 1e6, "algorithmic_bytes": alg,
-                "kernels": {k: {"launches": v[0], "avg_us": 1e3 * v[1] / v[0]} for k, v in
+                "chunk_rows": kc,
+                "kernels": {k: kernel_row(k, v, spec, kc) for k, v in
                             sorted(summary.items(), key=lambda kv: -kv[1][1])}}
     cpu = None
     if not args.no_cpu_baseline:

@@ -106,6 +106,11 @@ psv_status psv_grid_validate(const psv_grid* grid);
  * coefficients) and the workspace on the current device. */
 psv_status psv_plan_create(const psv_grid* grid, const psv_opts* opts, psv_plan** out);
 psv_status psv_plan_workspace_size(const psv_plan* plan, size_t* bytes);
+/* Launch shape the plan runs with (after autotuning): x lines per block and
+ * rows per chunk of the wall-normal partition (= planes per y tile; the z
+ * solve has 2 ceil(nz / chunk_rows) interface rows per wavenumber pair).
+ * Either output pointer may be NULL. */
+psv_status psv_plan_shape(const psv_plan* plan, int* lines_x, int* chunk_rows);
 psv_status psv_plan_destroy(psv_plan* plan);
 
 /* One or more chained solves (Sec. 3.3.1, Eq. poisson_me1).

@@ -134,6 +134,12 @@ class Plan:
         check(lib().psv_plan_workspace_size(self._h, C.byref(n)))
         return n.value
 
+    def launch_shape(self):
+        """(x lines per block, rows per chunk of the wall-normal partition)."""
+        lx, kc = C.c_int(), C.c_int()
+        check(lib().psv_plan_shape(self._h, C.byref(lx), C.byref(kc)))
+        return lx.value, kc.value
+
     def close(self):
         if getattr(self, "_h", None) and self._h.value:
             check(lib().psv_plan_destroy(self._h))

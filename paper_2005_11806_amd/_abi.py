@@ -42,6 +42,7 @@ EXPORTS = {
     "psv_grid_validate": (C.c_int, [C.POINTER(psv_grid)]),
     "psv_plan_create": (C.c_int, [C.POINTER(psv_grid), C.POINTER(psv_opts), C.POINTER(C.c_void_p)]),
     "psv_plan_workspace_size": (C.c_int, [C.c_void_p, C.POINTER(C.c_size_t)]),
+    "psv_plan_shape": (C.c_int, [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
     "psv_plan_destroy": (C.c_int, [C.c_void_p]),
     "psv_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_void_p, C.c_void_p,
                             C.c_int32, C.c_void_p, C.POINTER(psv_info)]),

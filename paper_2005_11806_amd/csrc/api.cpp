@@ -80,8 +80,9 @@ void check_field(const Plan& P, const double* x, bool positive, const char* name
 }
 
 // One constant-coefficient solve of the system assembled by `a` (CONST or
-// METHOD1), written to `out`. FP64: five passes. MIXED: the same passes in
-// FP32 followed by FP64 residual refinement until relres <= tol. Returns the
+// METHOD1), written to `out`. FP64: five passes (x, y with the z chunk
+// elimination, z interface, y with the back substitution, inverse x).
+// MIXED: the same passes in FP32 followed by FP64 residual refinement until relres <= tol. Returns the
 // number of refinement sweeps (MIXED) and leaves relres in scal[S_RELRES]
 // when it was computed.
 struct CoreResult {
@@ -102,9 +103,7 @@ CoreResult solve_core(Plan& P, psv::FwdArgs a, double* out, bool want_relres, hi
     a.partials = mixed ? P.partials : nullptr;
     launch_fwd_x(P, mixed, a, s);
     if (mixed) launch_mean_finalize(P, fwd_x_blocks(P), P.scal + S_RHS_MEAN, s);
-    launch_fft_y(P, mixed, false, nullptr, s);
-    launch_thomas(P, mixed, P.scal + (mixed ? S_MEAN2 : S_RHS_MEAN), nullptr, s);
-    launch_fft_y(P, mixed, true, nullptr, s);
+    launch_z_solve(P, mixed, P.scal + (mixed ? S_MEAN2 : S_RHS_MEAN), nullptr, s);
     launch_inv_x(P, mixed, INV_STORE, out, inv_scale, nullptr, s);
     if (!mixed) {
         if (want_relres) {
@@ -141,9 +140,7 @@ CoreResult solve_core(Plan& P, psv::FwdArgs a, double* out, bool want_relres, hi
         if (!fused) {
             launch_fwd_x(P, true, ra, s);
         }
-        launch_fft_y(P, true, false, nullptr, s);
-        launch_thomas(P, true, P.scal + S_MEAN2, nullptr, s);
-        launch_fft_y(P, true, true, nullptr, s);
+        launch_z_solve(P, true, P.scal + S_MEAN2, nullptr, s);
         launch_inv_x(P, true, INV_ADD, out, inv_scale, nullptr, s);
         res.steps++;
         fused = false;
@@ -190,6 +187,14 @@ psv_status psv_plan_workspace_size(const psv_plan* plan, size_t* bytes) {
     return guarded([&] {
         need(plan && bytes, "plan and bytes must be non-NULL");
         *bytes = plan->p.ws_bytes;
+    });
+}
+
+psv_status psv_plan_shape(const psv_plan* plan, int* lines_x, int* chunk_rows) {
+    return guarded([&] {
+        need(plan != nullptr, "plan is NULL");
+        if (lines_x) *lines_x = plan->p.lp.lbx;
+        if (chunk_rows) *chunk_rows = plan->p.lp.kc;
     });
 }
 

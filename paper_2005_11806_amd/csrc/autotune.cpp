@@ -1,11 +1,11 @@
-// Launch-shape autotuner of a plan: lines per x-block (lbx), planes per
-// y-tile (lby) and rows per lane of the tridiagonal solve (tri_L). Each pass is
-// timed with hipEvents on synthetic data for every candidate that fits the LDS
-// budget; the fastest per pass is kept, and the tuned solve must match the
+// Launch-shape autotuner of a plan: lines per x-block (lbx) and planes per
+// y tile, which are also the rows per chunk of the z partition (kc). Each is
+// timed with hipEvents on synthetic data for every candidate that fits the
+// LDS of a block; the fastest is kept, and the tuned solve must match the
 // default-shape solve (FP64: 1e-10, FP32 spectra: 1e-3 relative in the max
 // norm) or the defaults stay. Choices are cached per (arch, grid, precision,
 // method) in the process and, when PSV_AUTOTUNE_CACHE names a file, on disk
-// (one "key lbx lby tri_L" line per entry).
+// (one "key lbx kc" line per entry).
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -43,9 +43,13 @@ void load_cache() {
     const char* path = std::getenv("PSV_AUTOTUNE_CACHE");
     if (!path) return;
     std::ifstream in(path);
-    std::string key;
-    Launch l;
-    while (in >> key >> l.lbx >> l.lby >> l.tri_L) g_cache[key] = l;
+    std::string line;
+    while (std::getline(in, line)) {
+        std::istringstream ls(line);
+        std::string key, extra;
+        Launch l;
+        if ((ls >> key >> l.lbx >> l.kc) && !(ls >> extra)) g_cache[key] = l;
+    }
 }
 
 void store_cache(const std::string& key, const Launch& l) {
@@ -53,7 +57,7 @@ void store_cache(const std::string& key, const Launch& l) {
     const char* path = std::getenv("PSV_AUTOTUNE_CACHE");
     if (!path) return;
     std::ofstream out(path, std::ios::app);
-    out << key << " " << l.lbx << " " << l.lby << " " << l.tri_L << "\n";
+    out << key << " " << l.lbx << " " << l.kc << "\n";
 }
 
 // deterministic synthetic inputs: f, p_prev smooth-ish, rho in [1, 1000]
@@ -91,9 +95,7 @@ float time_ms(hipStream_t s, const std::function<void()>& fn) {
 void solve_once(const Plan& p, const FwdArgs& a, double* out, hipStream_t s) {
     const bool fp32 = p.opts.precision == PSV_MIXED;
     launch_fwd_x(p, fp32, a, s);
-    launch_fft_y(p, fp32, false, nullptr, s);
-    launch_thomas(p, fp32, p.scal + S_MEAN2, nullptr, s);
-    launch_fft_y(p, fp32, true, nullptr, s);
+    launch_z_solve(p, fp32, p.scal + S_MEAN2, nullptr, s);
     launch_inv_x(p, fp32, INV_STORE, out, 2.0 / ((double)p.nx * p.ny), nullptr, s);
 }
 
@@ -102,9 +104,6 @@ bool fits_x(const Plan& p, int lb) {
     return x_lds_max(p.nx, lb) <= 62 * 1024;
 }
 
-bool fits_y(const Plan& p, int kb) {
-    return ((size_t)2 * kb * (p.ny + 1) + p.ny) * sizeof(double2) <= 62 * 1024;
-}
 
 }  // namespace
 
@@ -114,10 +113,9 @@ void autotune_plan(Plan& p) {
     const std::string key = tune_key(p);
     auto it = g_cache.find(key);
     if (it != g_cache.end()) {
-        if (fits_x(p, it->second.lbx) && fits_y(p, it->second.lby)) {
+        if (fits_x(p, it->second.lbx) && kc_fits(p, it->second.kc)) {
             p.lp.lbx = it->second.lbx;
-            p.lp.lby = it->second.lby;
-            p.lp.tri_L = it->second.tri_L;
+            if (it->second.kc != p.lp.kc) plan_set_kc(p, it->second.kc);
             return;
         }
     }
@@ -150,25 +148,15 @@ void autotune_plan(Plan& p) {
     }
     p.lp.lbx = best.lbx;
     tbest = 1e30f;
-    for (int kb : {1, 2, 4, 8, 16}) {
-        if (!fits_y(p, kb)) continue;
-        p.lp.lby = kb;
-        const float t = time_ms(s, [&] { launch_fft_y(p, fp32, false, nullptr, s); }) +
-                        time_ms(s, [&] { launch_fft_y(p, fp32, true, nullptr, s); });
-        if (t < tbest) { tbest = t; best.lby = kb; }
+    for (int kc : {4, 8, 16}) {
+        if (!kc_fits(p, kc) || kc > 2 * p.nz) continue;
+        plan_set_kc(p, kc);
+        // the z solve keeps the spectrum finite on repeated application
+        launch_fwd_x(p, fp32, a, s);
+        const float t = time_ms(s, [&] { launch_z_solve(p, fp32, p.scal + S_MEAN2, nullptr, s); });
+        if (t < tbest) { tbest = t; best.kc = kc; }
     }
-    p.lp.lby = best.lby;
-    tbest = 1e30f;
-    for (int L : {4, 8, 16, 32}) {
-        int Lr = 8, P = 1;
-        tri_shape(p.nz, Lr, P, L);
-        if (Lr != L) continue;  // this L needs more than 64 lanes per system
-        p.lp.tri_L = L;
-        launch_fwd_x(p, fp32, a, s);  // fresh spectrum for every candidate
-        launch_fft_y(p, fp32, false, nullptr, s);
-        const float t = time_ms(s, [&] { launch_thomas(p, fp32, p.scal + S_MEAN2, nullptr, s); });
-        if (t < tbest) { tbest = t; best.tri_L = L; }
-    }
+    plan_set_kc(p, best.kc);
     p.lp = best;
     // parity of the tuned shapes against the default ones
     solve_once(p, a, out, s);
@@ -187,9 +175,9 @@ void autotune_plan(Plan& p) {
             std::fprintf(stderr, "psv autotune: %s tuned shapes failed parity (%.3e); keeping defaults\n",
                          key.c_str(), emax / vmax);
         p.lp = def;
+        plan_set_kc(p, def.kc);
     } else if (std::getenv("PSV_LOG")) {
-        std::fprintf(stderr, "psv autotune: %s -> lbx %d lby %d tri_L %d\n", key.c_str(), p.lp.lbx,
-                     p.lp.lby, p.lp.tri_L);
+        std::fprintf(stderr, "psv autotune: %s -> lbx %d kc %d\n", key.c_str(), p.lp.lbx, p.lp.kc);
     }
     store_cache(key, p.lp);
     (void)hipStreamDestroy(s);

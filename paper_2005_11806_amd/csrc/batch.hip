@@ -28,10 +28,10 @@ enum BKind : int {
     K_MINF,      // rho0: given value or the reduced minimum
     K_FWD,       // assembly + forward x (CONST or METHOD1)
     K_MEAN,      // FP64 volume-weighted mean of the RHS from the forward partials (mixed)
-    K_Y,         // forward y into layout B
-    K_Z,         // tridiagonal solves + zero mode (mean to S_RHS_MEAN)
+    K_Y,         // forward y + chunk elimination of the z solve
+    K_Z,         // z interface systems + zero mode (mean to S_RHS_MEAN)
     K_Z2,        // same, mean discarded (refinement corrections)
-    K_YI,        // inverse y into layout A
+    K_YI,        // z back substitution + inverse y
     K_INV,       // inverse x, store
     K_INVADD,    // inverse x, accumulate
     K_RES,       // fused residual + forward x (refinement)
@@ -49,12 +49,11 @@ struct ProblemDesc {
     XGeom xg;
     Stencil st;
     ZArgs z;  // rhs_mean set per kind at run time
-    int kb, L, method, fp32;
+    int method, fp32;
     Radices rad_y;
     const void* twx;
     const void* twy;
     void* spec;
-    void* spec_t;
     double* r_ws;
     double* partials;
     double* scal;
@@ -78,8 +77,8 @@ inline int kind_tiles(const Plan& p, int kind) {
     switch (kind) {
         case K_MINP: return std::min<int>(MAX_MIN_TILES, (int)((p.ncell() + MIN_TILE - 1) / MIN_TILE));
         case K_FWD: case K_INV: case K_INVADD: case K_RES: return fwd_x_blocks(p);
-        case K_Y: case K_YI: return fft_y_tiles(p);
-        case K_Z: case K_Z2: return tri_tiles(p);
+        case K_Y: case K_YI: return yz_tiles(p);
+        case K_Z: case K_Z2: return ifc_tiles(p);
         case K_CHK: return (int)((p.ncell() + RES_TILE - 1) / RES_TILE);
         default: return 1;
     }
@@ -189,7 +188,6 @@ __device__ void chk_tile(const ProblemDesc& D, const ProblemIO& io, int b, doubl
 // ---------------------------------------------------------------------------
 // device: one tile of one pass of one problem
 #define PSV_BX_SIZES(X) X(16) X(24) X(32) X(48) X(64) X(96) X(128)
-#define PSV_BY_SIZES(X) X(32) X(48) X(64) X(96) X(128) X(192) X(256)
 
 template <typename T, int MODE>
 __device__ __forceinline__ void run_fwd(const ProblemDesc& D, const FwdArgs& a, int b,
@@ -217,36 +215,36 @@ __device__ __forceinline__ void run_inv(const ProblemDesc& D, double* out, int b
     }
 }
 
-template <typename T, int DIR>
-__device__ __forceinline__ void run_y(const ProblemDesc& D, int b, unsigned char* smem) {
+template <typename T, bool INV, int N>
+__device__ __forceinline__ void yz_tile(const ProblemDesc& D, c2<T>* sp, const c2<T>* tw, int b,
+                                        unsigned char* smem) {
+    with_kc(D.z.kc, [&](auto kc) {
+        constexpr int KC = decltype(kc)::value;
+        if constexpr (INV)
+            yz_inv_tile<T, N, KC>(D.z, D.rad_y, sp, tw, b, smem);
+        else
+            yz_fwd_tile<T, N, KC>(D.z, D.rad_y, sp, tw, b, smem);
+    });
+}
+
+template <typename T, bool INV>
+__device__ __forceinline__ void run_yz(const ProblemDesc& D, int b, unsigned char* smem) {
     const c2<T>* tw = reinterpret_cast<const c2<T>*>(D.twy);
-    const c2<T>* in = reinterpret_cast<const c2<T>*>(DIR < 0 ? D.spec : D.spec_t);
-    c2<T>* out = reinterpret_cast<c2<T>*>(DIR < 0 ? D.spec_t : D.spec);
-    const int ny = D.xg.ny;
-    switch (ny) {
-#define PSV_CASE(n)                                                                     \
-    case n: fft_y_tile<T, T, DIR, n>(ny, D.xg.nz, D.xg.mx, D.kb, D.rad_y, in, out, tw, b, smem); \
-        return;
-        PSV_BY_SIZES(PSV_CASE)
+    c2<T>* sp = reinterpret_cast<c2<T>*>(D.spec);
+    switch (D.xg.ny) {
+#define PSV_CASE(n) case n: yz_tile<T, INV, n>(D, sp, tw, b, smem); return;
+        PSV_YZ_SIZES(PSV_CASE)
 #undef PSV_CASE
-        default: fft_y_tile<T, T, DIR, 0>(ny, D.xg.nz, D.xg.mx, D.kb, D.rad_y, in, out, tw, b, smem);
-            return;
+        default: yz_tile<T, INV, 0>(D, sp, tw, b, smem); return;
     }
 }
 
 template <typename T>
-__device__ __forceinline__ void run_z(const ProblemDesc& D, double* mean_out, int b,
-                                      unsigned char* smem) {
+__device__ __forceinline__ void run_ifc(const ProblemDesc& D, double* mean_out, int b,
+                                        unsigned char* smem) {
     ZArgs z = D.z;
     z.rhs_mean = mean_out;
-    c2<T>* sp = reinterpret_cast<c2<T>*>(D.spec_t);
-    switch (D.L) {
-        case 2: tri_tile<T, 2>(z, sp, b, smem); return;
-        case 4: tri_tile<T, 4>(z, sp, b, smem); return;
-        case 8: tri_tile<T, 8>(z, sp, b, smem); return;
-        case 16: tri_tile<T, 16>(z, sp, b, smem); return;
-        default: tri_tile<T, 32>(z, sp, b, smem); return;
-    }
+    ifc_tile<T>(z, reinterpret_cast<c2<T>*>(D.spec), b, smem);
 }
 
 template <typename T, int KIND>
@@ -278,13 +276,13 @@ __device__ __forceinline__ void run_task(const ProblemDesc& D, const ProblemIO& 
     } else if constexpr (KIND == K_MEAN) {
         mean_tile(D, red);
     } else if constexpr (KIND == K_Y) {
-        run_y<T, -1>(D, b, smem);
+        run_yz<T, false>(D, b, smem);
     } else if constexpr (KIND == K_YI) {
-        run_y<T, +1>(D, b, smem);
+        run_yz<T, true>(D, b, smem);
     } else if constexpr (KIND == K_Z) {
-        run_z<T>(D, D.scal + (D.fp32 ? S_MEAN2 : S_RHS_MEAN), b, smem);
+        run_ifc<T>(D, D.scal + (D.fp32 ? S_MEAN2 : S_RHS_MEAN), b, smem);
     } else if constexpr (KIND == K_Z2) {
-        run_z<T>(D, D.scal + S_MEAN2, b, smem);
+        run_ifc<T>(D, D.scal + S_MEAN2, b, smem);
     } else if constexpr (KIND == K_INV) {
         run_inv<T, INV_STORE>(D, io.pout, b, smem);
     } else if constexpr (KIND == K_INVADD) {
@@ -457,12 +455,8 @@ static size_t kind_lds(const Plan& p, int kind, bool fp32) {
     switch (kind) {
         case K_FWD: case K_RES: return fwd_x_lds(g, cs);
         case K_INV: case K_INVADD: return inv_x_lds(g, cs);
-        case K_Y: case K_YI: return fft_y_lds(p.ny, p.lp.lby, cs);
-        case K_Z: case K_Z2: {
-            int L = 8, P = 1;
-            tri_shape(p, L, P);
-            return fp32 ? tri_lds<float>(L) : tri_lds<double>(L);
-        }
+        case K_Y: case K_YI: return yz_lds(p.ny, p.lp.kc, cs);
+        case K_Z: case K_Z2: return ifc_lds(p);
         default: return 0;
     }
 }
@@ -472,6 +466,7 @@ static void launch_pass(const psv_batch& B, const PassLaunch& L, hipStream_t s) 
     switch (L.kind) {
 #define PSV_K(k)                                                                             \
     case k:                                                                                  \
+        allow_lds(k_batch_pass<T, k>, L.lds);                                                \
         hipLaunchKernelGGL((k_batch_pass<T, k>), dim3(L.nblk), dim3(256), L.lds, s, B.d_desc, \
                            B.d_io, L.d_start, B.n);                                         \
         break;
@@ -568,6 +563,7 @@ static void launch_persistent(const psv_batch& B, int gi, hipStream_t s) {
     hipLaunchKernelGGL(k_persist_reset, dim3((rn + 255) / 256), dim3(256), 0, s, B.d_desc, B.n,
                        B.d_counters, ncount, B.d_ticket, B.d_ticket + 1);
     int per_cu = 0, ncu = 0;
+    allow_lds(k_batch_persistent<T>, B.plds[gi]);
     PSV_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_persistent<T>, 256,
                                                          B.plds[gi]));
     PSV_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, B.device));
@@ -616,17 +612,12 @@ void batch_create(psv_batch& B, int n, const psv_grid* grids, const psv_opts& o)
         D.xg = make_xgeom(*pl);
         D.st = Stencil{pl->t.inv_h, pl->t.inv_g, pl->t.vol};
         D.z = make_zargs(*pl, pl->scal + S_RHS_MEAN);
-        D.kb = pl->lp.lby;
-        int L = 8, P = 1;
-        tri_shape(*pl, L, P);
-        D.L = L;
         D.method = o.method;
         D.fp32 = B.fp32 ? 1 : 0;
         D.rad_y = pl->rad_y;
         D.twx = B.fp32 ? (const void*)pl->t.twx32 : (const void*)pl->t.twx64;
         D.twy = B.fp32 ? (const void*)pl->t.twy32 : (const void*)pl->t.twy64;
         D.spec = pl->spec;
-        D.spec_t = pl->spec_t;
         D.r_ws = pl->r_ws;
         D.partials = pl->partials;
         D.scal = pl->scal;

@@ -187,10 +187,11 @@ __host__ __device__ constexpr int radix_prefix(RadixList L, int s) {
     return p;
 }
 
+// Butterfly j of a radix-R Stockham stage (NS = product of the earlier
+// radices, NB = N / R): load with twiddles and transform into v, then store.
 template <int R, int DIR, int NS, int NB, int TSTEP, typename C>
-__device__ __forceinline__ void stockham_bfly_ct(const C* __restrict__ in, C* __restrict__ out,
-                                                 int j, const C* __restrict__ tw) {
-    C v[R];
+__device__ __forceinline__ void stockham_load_ct(const C* __restrict__ in, int j,
+                                                 const C* __restrict__ tw, C* v) {
 #pragma unroll
     for (int r = 0; r < R; ++r) v[r] = in[j + r * NB];
     const int k = j % NS;
@@ -206,9 +207,21 @@ __device__ __forceinline__ void stockham_bfly_ct(const C* __restrict__ in, C* __
     if (R == 3) bfly3<DIR>(v);
     if (R == 4) bfly4<DIR>(v);
     if (R == 8) bfly8<DIR>(v);
-    const int base = (j / NS) * NS * R + k;
+}
+
+template <int R, int NS, typename C>
+__device__ __forceinline__ void stockham_store_ct(C* __restrict__ out, int j, const C* v) {
+    const int base = (j / NS) * NS * R + j % NS;
 #pragma unroll
     for (int r = 0; r < R; ++r) out[base + r * NS] = v[r];
+}
+
+template <int R, int DIR, int NS, int NB, int TSTEP, typename C>
+__device__ __forceinline__ void stockham_bfly_ct(const C* __restrict__ in, C* __restrict__ out,
+                                                 int j, const C* __restrict__ tw) {
+    C v[R];
+    stockham_load_ct<R, DIR, NS, NB, TSTEP>(in, j, tw, v);
+    stockham_store_ct<R, NS>(out, j, v);
 }
 
 template <int N, int S, int DIR, int TWM, typename C>
@@ -231,6 +244,50 @@ __device__ __forceinline__ C* fft_stages(C* src, C* dst, int nlines, int lstride
         __syncthreads();
         return fft_stages<N, S + 1, DIR, TWM>(dst, src, nlines, lstride, tw);
     }
+}
+
+// In-place variant for NL lines of length N stored contiguously in one LDS
+// buffer: every stage reads all of its butterflies into registers (a thread
+// takes butterflies t, t + 256, ...), waits for the block, then writes. Ends
+// with the block synchronised.
+template <int N, int S, int DIR, int TWM, int NL, typename C>
+__device__ __forceinline__ void fft_inplace(C* buf, const C* __restrict__ tw) {
+    constexpr RadixList RL = radix_list(N);
+    if constexpr (S < RL.count) {
+        constexpr int R = RL.r[S];
+        constexpr int NS = radix_prefix(RL, S);
+        constexpr int NB = N / R;
+        constexpr int TSTEP = (N / (NS * R)) * TWM;
+        constexpr int TOTAL = NL * NB;
+        constexpr int IT = (TOTAL + 255) / 256;
+        C v[IT][R];
+#pragma unroll
+        for (int it = 0; it < IT; ++it) {
+            const int t = (int)threadIdx.x + it * 256;
+            if (TOTAL % 256 == 0 || t < TOTAL) {
+                const int line = t / NB;
+                stockham_load_ct<R, DIR, NS, NB, TSTEP>(buf + line * N, t - line * NB, tw, v[it]);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int it = 0; it < IT; ++it) {
+            const int t = (int)threadIdx.x + it * 256;
+            if (TOTAL % 256 == 0 || t < TOTAL) {
+                const int line = t / NB;
+                stockham_store_ct<R, NS>(buf + line * N, t - line * NB, v[it]);
+            }
+        }
+        __syncthreads();
+        fft_inplace<N, S + 1, DIR, TWM, NL>(buf, tw);
+    }
+}
+
+// 1/s: hardware reciprocal refined by two Newton steps
+__device__ __forceinline__ double rcp_nr(double s) {
+    double r = __builtin_amdgcn_rcp(s);
+    r = fma(r, fma(-s, r, 1.0), r);
+    return fma(r, fma(-s, r, 1.0), r);
 }
 
 // N = 0 selects the runtime-length routine above.

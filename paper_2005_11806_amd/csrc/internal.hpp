@@ -22,6 +22,18 @@ struct Error {
 void hip_check(hipError_t e, const char* what);
 #define PSV_HIP(call) ::psv::hip_check((call), #call)
 
+// LDS a block may take on gfx950 (160 KiB), less room for static arrays
+constexpr int LDS_MAX_BLOCK = 152 * 1024;
+
+// Lets `kernel` take more than 64 KiB of dynamic LDS; a no-op below that.
+template <typename K>
+void allow_lds(K kernel, size_t bytes) {
+    if (bytes > 65536)
+        hip_check(hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes),
+                  "hipFuncSetAttribute");
+}
+
 // Radix sequence of a 2^a 3^b length (8s, then 4 / 2, then 3s).
 Radices make_radices(int n);
 
@@ -71,12 +83,8 @@ struct DevTables {
 };
 
 struct Launch {
-    int lbx = 8;       // lines per block, x passes
-    int lby = 8;       // lines per block, y passes
-    int thr_x = 256;
-    int thr_y = 256;
-    int thr_z = 256;
-    int tri_L = 8;     // preferred rows per lane of the tridiagonal solve
+    int lbx = 8;  // lines per block, x passes
+    int kc = 8;   // planes per y tile = rows per chunk of the z partition
 };
 
 // Launch-shape autotuning (autotune.cpp): times candidate shapes per pass on
@@ -126,8 +134,9 @@ struct Plan {
     Launch lp;
     int device = 0;
     // workspace
-    void* spec = nullptr;      // layout A [nz][mx][ny] complex, FP64 or FP32
-    void* spec_t = nullptr;    // layout B [mx][ny][nz]: one wall-normal system per column
+    void* spec = nullptr;      // spectrum [nz][mx][ny] complex, FP64 or FP32
+    void* ifc_tab = nullptr;   // interface factors of the z partition (plan's precision)
+    size_t ifc_tab_bytes = 0;
     double* r_ws = nullptr;    // FP64 right-hand side [N]
     double* partials = nullptr;
     int n_partials = 0;
@@ -160,8 +169,16 @@ struct FwdArgs {
     const int* done;      // skip when *done != 0 (may be null)
 };
 void launch_fwd_x(const Plan& p, bool fp32, const FwdArgs& a, hipStream_t s);
-void launch_fft_y(const Plan& p, bool fp32, bool inverse, const int* done, hipStream_t s);
-void launch_thomas(const Plan& p, bool fp32, double* mean_out, const int* done, hipStream_t s);
+// y passes with the chunk elimination (forward) or back substitution
+// (inverse) of the z solve, the interface pass between them, and the three
+// in order; mean_out receives the volume-weighted mean of the RHS.
+void launch_yz(const Plan& p, bool fp32, bool inverse, const int* done, hipStream_t s);
+void launch_interface(const Plan& p, bool fp32, double* mean_out, const int* done, hipStream_t s);
+void launch_z_solve(const Plan& p, bool fp32, double* mean_out, const int* done, hipStream_t s);
+// Chunk rows of the z partition: whether kc fits, and setting it (recomputes
+// the interface factor table, synchronising).
+bool kc_fits(const Plan& p, int kc);
+void plan_set_kc(Plan& p, int kc);
 void launch_inv_x(const Plan& p, bool fp32, int mode, double* out, double scale_all,
                   const int* done, hipStream_t s);
 

@@ -1,94 +1,151 @@
-// Per-pass kernels of the y and z directions (tile bodies in pass_yz.hpp).
+// Per-pass kernels of the y and z directions (tile bodies in pass_yz.hpp) and
+// the plan-time interface factor table.
 #include "pass_yz.hpp"
 
 namespace psv {
 namespace {
 
-template <typename TS, typename TC, int DIR, int N>
-__global__ void __launch_bounds__(256) k_fft_y_t(int ny_rt, int nz, int mx, int kb, Radices rad,
-                                                  const c2<TS>* __restrict__ in,
-                                                  c2<TS>* __restrict__ out,
-                                                  const c2<TC>* __restrict__ tw_g, const int* done) {
+template <typename T, int N, int KC, bool INV>
+__global__ void __launch_bounds__(256) k_yz(ZArgs z, Radices rad, c2<T>* __restrict__ spec,
+                                            const c2<T>* __restrict__ tw_g, const int* done) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     if (done && *done) return;
-    fft_y_tile<TS, TC, DIR, N>(ny_rt, nz, mx, kb, rad, in, out, tw_g, blockIdx.x, smem_raw);
-}
-
-template <typename T, int L>
-__global__ void __launch_bounds__(256) k_tri_wave(ZArgs z, c2<T>* __restrict__ spec, const int* done) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    if (done && *done) return;
-    tri_tile<T, L>(z, spec, blockIdx.x, smem_raw);
-}
-
-// y-line lengths with a compile-time FFT; others use the runtime one
-#define PSV_Y_SIZES(X) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(512)
-
-template <typename T, int DIR>
-void fft_y_dispatch(const Plan& p, int nblk, int kb, const c2<T>* in, c2<T>* out, const c2<T>* tw,
-                    const int* done, hipStream_t s) {
-    const size_t lds = fft_y_lds(p.ny, kb, sizeof(c2<T>));
-    switch (p.ny) {
-#define PSV_CASE(n)                                                                               \
-    case n:                                                                                       \
-        hipLaunchKernelGGL((k_fft_y_t<T, T, DIR, n>), dim3(nblk), dim3(256), lds, s, p.ny, p.nz, \
-                           p.mx, kb, p.rad_y, in, out, tw, done);                                 \
-        break;
-        PSV_Y_SIZES(PSV_CASE)
-#undef PSV_CASE
-        default:
-            hipLaunchKernelGGL((k_fft_y_t<T, T, DIR, 0>), dim3(nblk), dim3(256), lds, s, p.ny, p.nz,
-                               p.mx, kb, p.rad_y, in, out, tw, done);
-            break;
-    }
+    if constexpr (INV)
+        yz_inv_tile<T, N, KC>(z, rad, spec, tw_g, blockIdx.x, smem_raw);
+    else
+        yz_fwd_tile<T, N, KC>(z, rad, spec, tw_g, blockIdx.x, smem_raw);
 }
 
 template <typename T>
-void tri_launch(const ZArgs& z, int L, int nblk, void* spec, const int* done, hipStream_t s) {
-    c2<T>* sp = reinterpret_cast<c2<T>*>(spec);
-    const size_t lds = tri_lds<T>(L);
-    switch (L) {
-        case 2: hipLaunchKernelGGL((k_tri_wave<T, 2>), dim3(nblk), dim3(256), lds, s, z, sp, done); break;
-        case 4: hipLaunchKernelGGL((k_tri_wave<T, 4>), dim3(nblk), dim3(256), lds, s, z, sp, done); break;
-        case 8: hipLaunchKernelGGL((k_tri_wave<T, 8>), dim3(nblk), dim3(256), lds, s, z, sp, done); break;
-        case 16: hipLaunchKernelGGL((k_tri_wave<T, 16>), dim3(nblk), dim3(256), lds, s, z, sp, done); break;
-        default: hipLaunchKernelGGL((k_tri_wave<T, 32>), dim3(nblk), dim3(256), lds, s, z, sp, done); break;
+__global__ void __launch_bounds__(IFC_SYS) k_ifc(ZArgs z, c2<T>* __restrict__ spec, const int* done) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    if (done && *done) return;
+    ifc_tile<T>(z, spec, blockIdx.x, smem_raw);
+}
+
+constexpr int TAB_THREADS = 64;
+
+template <typename T>
+__global__ void __launch_bounds__(TAB_THREADS) k_ifc_table(ZArgs z, T* __restrict__ tab) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int s = blockIdx.x * TAB_THREADS + (int)threadIdx.x;
+    if (s >= z.mx * z.ny) return;
+    c2<T>* scratch = reinterpret_cast<c2<T>*>(smem_raw) + threadIdx.x;
+    ifc_table_pair<T>(z, s, tab, scratch, TAB_THREADS);
+}
+
+template <typename T, int N, int KC, bool INV>
+void yz_launch(const Plan& p, const ZArgs& z, c2<T>* spec, const c2<T>* tw, const int* done,
+               hipStream_t s) {
+    const size_t lds = yz_lds(p.ny, KC, sizeof(c2<T>));
+    allow_lds(k_yz<T, N, KC, INV>, lds);
+    hipLaunchKernelGGL((k_yz<T, N, KC, INV>), dim3(yz_tiles(p)), dim3(256), lds, s, z, p.rad_y,
+                       spec, tw, done);
+}
+
+template <typename T, int N, bool INV>
+void yz_dispatch_kc(const Plan& p, const ZArgs& z, c2<T>* spec, const c2<T>* tw, const int* done,
+                    hipStream_t s) {
+    switch (p.lp.kc) {
+        case 4: yz_launch<T, N, 4, INV>(p, z, spec, tw, done, s); break;
+        case 8: yz_launch<T, N, 8, INV>(p, z, spec, tw, done, s); break;
+        default: yz_launch<T, N, 16, INV>(p, z, spec, tw, done, s); break;
     }
+}
+
+template <typename T, bool INV>
+void yz_dispatch(const Plan& p, const ZArgs& z, c2<T>* spec, const c2<T>* tw, const int* done,
+                 hipStream_t s) {
+    switch (p.ny) {
+#define PSV_CASE(n) case n: yz_dispatch_kc<T, n, INV>(p, z, spec, tw, done, s); break;
+        PSV_YZ_SIZES(PSV_CASE)
+#undef PSV_CASE
+        default: yz_dispatch_kc<T, 0, INV>(p, z, spec, tw, done, s); break;
+    }
+}
+
+void check_precision(const Plan& p, bool fp32) {
+    if (fp32 != (p.opts.precision == PSV_MIXED))
+        fail(PSV_ERR_INVALID_ARG, "z pass precision differs from the plan's");
 }
 
 }  // namespace
 
-void launch_fft_y(const Plan& p, bool fp32, bool inverse, const int* done, hipStream_t s) {
-    const int kb = p.lp.lby;
-    const int nblk = fft_y_tiles(p);
-    static const char* names[2][2] = {{"fft_y_fwd_fp64", "fft_y_inv_fp64"},
-                                      {"fft_y_fwd_fp32", "fft_y_inv_fp32"}};
+void launch_yz(const Plan& p, bool fp32, bool inverse, const int* done, hipStream_t s) {
+    check_precision(p, fp32);
+    static const char* names[2][2] = {{"yz_fwd_fp64", "yz_inv_fp64"}, {"yz_fwd_fp32", "yz_inv_fp32"}};
     TraceScope ts(p, names[fp32][inverse], s);
+    const ZArgs z = make_zargs(p, nullptr);
     if (fp32) {
         if (inverse)
-            fft_y_dispatch<float, +1>(p, nblk, kb, (const float2*)p.spec_t, (float2*)p.spec, p.t.twy32, done, s);
+            yz_dispatch<float, true>(p, z, (float2*)p.spec, p.t.twy32, done, s);
         else
-            fft_y_dispatch<float, -1>(p, nblk, kb, (const float2*)p.spec, (float2*)p.spec_t, p.t.twy32, done, s);
+            yz_dispatch<float, false>(p, z, (float2*)p.spec, p.t.twy32, done, s);
     } else {
         if (inverse)
-            fft_y_dispatch<double, +1>(p, nblk, kb, (const double2*)p.spec_t, (double2*)p.spec, p.t.twy64, done, s);
+            yz_dispatch<double, true>(p, z, (double2*)p.spec, p.t.twy64, done, s);
         else
-            fft_y_dispatch<double, -1>(p, nblk, kb, (const double2*)p.spec, (double2*)p.spec_t, p.t.twy64, done, s);
+            yz_dispatch<double, false>(p, z, (double2*)p.spec, p.t.twy64, done, s);
     }
     PSV_HIP(hipGetLastError());
 }
 
-void launch_thomas(const Plan& p, bool fp32, double* mean_out, const int* done, hipStream_t s) {
+void launch_interface(const Plan& p, bool fp32, double* mean_out, const int* done, hipStream_t s) {
+    check_precision(p, fp32);
     const ZArgs z = make_zargs(p, mean_out);
-    int L = 8, P = 1;
-    tri_shape(p, L, P);
-    const int nblk = tri_tiles(p);
-    TraceScope ts(p, fp32 ? "thomas_z_fp32" : "thomas_z_fp64", s);
-    if (fp32)
-        tri_launch<float>(z, L, nblk, p.spec_t, done, s);
-    else
-        tri_launch<double>(z, L, nblk, p.spec_t, done, s);
+    const int nblk = ifc_tiles(p);
+    const size_t lds = ifc_lds(p);
+    TraceScope ts(p, fp32 ? "z_interface_fp32" : "z_interface_fp64", s);
+    if (fp32) {
+        allow_lds(k_ifc<float>, lds);
+        hipLaunchKernelGGL(k_ifc<float>, dim3(nblk), dim3(IFC_SYS), lds, s, z, (float2*)p.spec, done);
+    } else {
+        allow_lds(k_ifc<double>, lds);
+        hipLaunchKernelGGL(k_ifc<double>, dim3(nblk), dim3(IFC_SYS), lds, s, z, (double2*)p.spec, done);
+    }
     PSV_HIP(hipGetLastError());
+}
+
+void launch_z_solve(const Plan& p, bool fp32, double* mean_out, const int* done, hipStream_t s) {
+    launch_yz(p, fp32, false, done, s);
+    launch_interface(p, fp32, mean_out, done, s);
+    launch_yz(p, fp32, true, done, s);
+}
+
+bool kc_fits(const Plan& p, int kc) {
+    if (kc != 4 && kc != 8 && kc != 16) return false;
+    const size_t csz = p.opts.precision == PSV_MIXED ? sizeof(float2) : sizeof(double2);
+    return yz_lds(p.ny, kc, csz) <= (size_t)LDS_MAX_BLOCK;
+}
+
+void plan_set_kc(Plan& p, int kc) {
+    if (!kc_fits(p, kc)) fail(PSV_ERR_UNSUPPORTED_SIZE, "chunk rows do not fit the LDS of a block");
+    const bool fp32 = p.opts.precision == PSV_MIXED;
+    const size_t esz = fp32 ? sizeof(float) : sizeof(double);
+    const int nc = (p.nz + kc - 1) / kc;
+    const size_t bytes = (size_t)3 * 2 * nc * p.mx * p.ny * esz;
+    if (bytes > p.ifc_tab_bytes) {
+        if (p.ifc_tab) PSV_HIP(hipFree(p.ifc_tab));
+        p.ifc_tab = nullptr;
+        p.ifc_tab_bytes = 0;
+        PSV_HIP(hipMalloc(&p.ifc_tab, bytes));
+        p.ifc_tab_bytes = bytes;
+    }
+    p.lp.kc = kc;
+    const ZArgs z = make_zargs(p, nullptr);
+    const int nblk = (p.mx * p.ny + TAB_THREADS - 1) / TAB_THREADS;
+    const size_t lds = (size_t)kc * TAB_THREADS * (fp32 ? sizeof(float2) : sizeof(double2));
+    if (fp32) {
+        allow_lds(k_ifc_table<float>, lds);
+        hipLaunchKernelGGL(k_ifc_table<float>, dim3(nblk), dim3(TAB_THREADS), lds, nullptr, z,
+                           (float*)p.ifc_tab);
+    } else {
+        allow_lds(k_ifc_table<double>, lds);
+        hipLaunchKernelGGL(k_ifc_table<double>, dim3(nblk), dim3(TAB_THREADS), lds, nullptr, z,
+                           (double*)p.ifc_tab);
+    }
+    PSV_HIP(hipGetLastError());
+    PSV_HIP(hipDeviceSynchronize());
 }
 
 }  // namespace psv

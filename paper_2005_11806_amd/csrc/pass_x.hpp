@@ -46,13 +46,6 @@ inline size_t x_lds_max(int nx, int lb) {
     return a > b ? a : b;
 }
 
-// 1/s from the hardware estimate and two Newton steps
-__device__ __forceinline__ double rcp_nr(double s) {
-    double r = __builtin_amdgcn_rcp(s);
-    r = fma(r, fma(-s, r, 1.0), r);
-    return fma(r, fma(-s, r, 1.0), r);
-}
-
 // (1 - rho0/rho_f) (p_R - p_L) across the face between cells L and R, with
 // rho_f = (rho_L + rho_R)/2, i.e. (s - 2 rho0)/s with s = rho_L + rho_R.
 __device__ __forceinline__ double bflux(double rl, double rr, double pl, double pr, double two_r0) {

@@ -2,77 +2,60 @@
 // tile functions (256 threads), shared by the per-pass kernels and the
 // persistent batch kernel.
 //
-// Spectrum layouts: A = [k][m][n] (written and read by the x passes, y lines
-// contiguous) and B = [m][n][k] (one wall-normal system per contiguous column).
-//  * forward y tile: FFT along y of the lines of A, stored transposed into B
-//    (a tile is one m and kb consecutive planes, so every store run is kb
-//    consecutive k);
-//  * z tile: one tridiagonal solve per wavenumber pair (m, n) != (0, 0),
-//      a_k x_{k-1} + (b_k + lx[m] + ly[n]) x_k + c_k x_{k+1} = R_k,
-//    by a partition method in registers: P lanes per system each own L
-//    consecutive rows, eliminate them to two interface rows, the 2P-row
-//    interface system is solved by parallel cyclic reduction over wave
-//    shuffles, then the interior rows are recovered;
-//  * the singular (0, 0) pair in FP64: projection of the right-hand side
-//    (removal of its volume-weighted mean), flux integration from the bottom
-//    wall, gauge sum_k h_k x_k = 0;
-//  * inverse y tile: B back to A with the inverse FFT along y.
+// The spectrum keeps one layout, [k][m][n] (plane k, x wavenumber m, y
+// wavenumber n; y lines contiguous), through every pass. For every
+// wavenumber pair (m, n) != (0, 0) the wall-normal system
+//     a_k x_{k-1} + (b_k + lx[m] + ly[n]) x_k + c_k x_{k+1} = R_k
+// is solved by a partition method whose chunks are the y tiles themselves:
+//  * forward y tile: kc consecutive planes of one m, all n: the FFT along y
+//    of its kc lines, then, per n, the local elimination of the chunk's rows
+//    (forward sweep, and a backward sweep that reduces row 0), leaving
+//      row 0:      A x_{last of previous chunk} + x_first + C x_last = d_0
+//      row i:      aa_i x_first + x_i + cc_i x_{i+1} = d_i   (0 < i < kc-1)
+//      row kc-1:   aa x_first + x_last + cc x_{first of next chunk} = d_{kc-1}
+//    written back in place;
+//  * interface pass: per pair, the 2 nc rows (first, last) of its nc chunks
+//    form a tridiagonal system with unit diagonal, solved by Thomas with the
+//    factors precomputed per plan (they do not depend on the data); its tile
+//    0 solves the singular (0, 0) pair in FP64: projection of the right-hand
+//    side (removal of its volume-weighted mean), flux integration from the
+//    bottom wall, gauge sum_k h_k x_k = 0;
+//  * inverse y tile: back substitution of the interior rows from x_first and
+//    x_last, then the inverse FFT along y, in place.
+// The elimination coefficients of every row are recomputed where they are
+// needed (one division per row), so the z solve adds no pass over the
+// spectrum: only the interface rows are read and written once more.
 #pragma once
+
+#include <type_traits>
 
 #include "internal.hpp"
 
 namespace psv {
 
-inline size_t fft_y_lds(int ny, int kb, size_t csz) { return ((size_t)2 * kb * (ny + 1) + ny) * csz; }
+// y-line lengths with a compile-time FFT (in place in one LDS buffer); other
+// lengths use the runtime FFT, which ping-pongs between two buffers
+#define PSV_YZ_SIZES(X) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(512)
+inline bool yz_compiled(int ny) {
+    switch (ny) {
+#define PSV_CASE(n) case n:
+        PSV_YZ_SIZES(PSV_CASE)
+#undef PSV_CASE
+        return true;
+        default: return false;
+    }
+}
 
-// N = ny as a compile-time constant, or 0 for the runtime-length FFT.
-template <typename TS, typename TC, int DIR, int N>
-__device__ __forceinline__ void fft_y_tile(int ny_rt, int nz, int mx, int kb, const Radices& rad,
-                                           const c2<TS>* __restrict__ in, c2<TS>* __restrict__ out,
-                                           const c2<TC>* __restrict__ tw_g, int b,
-                                           unsigned char* smem) {
-    using C = c2<TC>;
-    const int ny = N ? N : ny_rt;
-    const int ls = ny + 1;  // padded line stride: transposed LDS accesses hit distinct banks
-    C* buf0 = reinterpret_cast<C*>(smem);
-    C* buf1 = buf0 + kb * ls;
-    C* tw = buf1 + kb * ls;  // exp(-2 pi i t / ny), t < ny
-    for (int t = threadIdx.x; t < ny; t += 256) tw[t] = tw_g[t];
-    const int kchunks = (nz + kb - 1) / kb;
-    const int m = b / kchunks;
-    const int k0 = (b - m * kchunks) * kb;
-    const int nl = min(kb, nz - k0);
-    const int n_el = nl * ny;
-    if (DIR < 0) {  // A -> LDS: nl contiguous lines of ny
-        for (int t = threadIdx.x; t < n_el; t += 256) {
-            const int q = t / ny, n = t - q * ny;
-            buf0[q * ls + n] = cconv<C>(in[((size_t)(k0 + q) * mx + m) * ny + n]);
-        }
-    } else {  // B -> LDS: runs of nl consecutive k per n
-        for (int t = threadIdx.x; t < n_el; t += 256) {
-            const int n = t / nl, q = t - n * nl;
-            buf0[q * ls + n] = cconv<C>(in[((size_t)m * ny + n) * nz + k0 + q]);
-        }
-    }
-    __syncthreads();
-    C* r = lds_fft_n<N, DIR, 1>(buf0, buf1, ny, nl, ls, rad, tw);
-    if (DIR < 0) {  // LDS -> B
-        for (int t = threadIdx.x; t < n_el; t += 256) {
-            const int n = t / nl, q = t - n * nl;
-            out[((size_t)m * ny + n) * nz + k0 + q] = cconv<c2<TS>>(r[q * ls + n]);
-        }
-    } else {  // LDS -> A
-        for (int t = threadIdx.x; t < n_el; t += 256) {
-            const int q = t / ny, n = t - q * ny;
-            out[((size_t)(k0 + q) * mx + m) * ny + n] = cconv<c2<TS>>(r[q * ls + n]);
-        }
-    }
+// LDS of a y tile: kc lines (two buffers of them for a runtime length) and
+// the twiddle table
+inline size_t yz_lds(int ny, int kc, size_t csz) {
+    return ((size_t)(yz_compiled(ny) ? 1 : 2) * kc * ny + ny) * csz;
 }
 
 struct ZArgs {
     int nz, mx, ny;
-    int P;           // lanes per system (power of 2, <= 64)
-    float rcp_nz;    // 1/nz, for splitting staged element indices
+    int kc;          // rows per chunk = planes per y tile (4, 8 or 16)
+    int nc;          // chunks per column, ceil(nz / kc)
     double nxny_lz;  // nx * ny * lz
     double lz;
     const double* za;
@@ -83,7 +66,226 @@ struct ZArgs {
     const double* h;
     const double* g;  // centre gaps, g[k] between cells k-1 and k
     double* rhs_mean;
+    const void* tab;  // interface factors, 3 arrays [2 nc][mx ny] in the spectrum's precision
 };
+
+// Row k of the system with eigenvalue sum lam; rows k >= nz pad the last
+// chunk as identity rows.
+struct ZRow {
+    double a, b, c;
+};
+__device__ __forceinline__ ZRow zrow(const ZArgs& z, int k, double lam) {
+    if (k < z.nz) return ZRow{z.za[k], z.zb[k] + lam, z.zc[k]};
+    return ZRow{0.0, 1.0, 0.0};
+}
+
+// Forward elimination of chunk row i given the reduced row i-1: row i
+// becomes aa x_first + x_i + cc x_{i+1} = d (for i = 0, aa couples to the
+// previous chunk's last unknown). Returns the pivot reciprocal.
+template <typename T>
+__device__ __forceinline__ double chunk_fwd(int i, const ZRow& w, T aa_prev, T cc_prev, T& aa,
+                                            T& cc) {
+    double r;
+    if (i < 2) {
+        r = rcp_nr(w.b);
+        aa = (T)(w.a * r);
+    } else {
+        r = rcp_nr(w.b - w.a * (double)cc_prev);
+        aa = (T)(-w.a * (double)aa_prev * r);
+    }
+    cc = (T)(w.c * r);
+    return r;
+}
+
+template <typename T>
+__device__ __forceinline__ c2<T> chunk_fwd_rhs(int i, const ZRow& w, double r, c2<T> d, c2<T> dp) {
+    if (i < 2) return c2<T>{(T)(d.x * r), (T)(d.y * r)};
+    return c2<T>{(T)((d.x - w.a * dp.x) * r), (T)((d.y - w.a * dp.y) * r)};
+}
+
+// One backward step over interior row i: with row i+1 in the form
+// ab x_first + x_{i+1} + cb x_last = db, row i takes the same form.
+template <typename T>
+__device__ __forceinline__ void chunk_bwd(T aa, T cc, T& ab, T& cb) {
+    ab = aa - cc * ab;
+    cb = -cc * cb;
+}
+template <typename T>
+__device__ __forceinline__ c2<T> chunk_bwd_rhs(c2<T> d, T cc, c2<T> db) {
+    return c2<T>{d.x - cc * db.x, d.y - cc * db.y};
+}
+template <typename T>
+__device__ __forceinline__ T chunk_row0_pivot(T cc0, T ab1) {
+    return (T)1 / ((T)1 - cc0 * ab1);
+}
+
+// Local elimination of one system's chunk (rows col[i * stride], i < KC, in
+// LDS), in registers: forward sweep, and the backward sweep that reduces row
+// 0; rows 1..KC-1 keep their forward-swept right-hand sides.
+template <typename T, int KC>
+__device__ __forceinline__ void chunk_eliminate(const ZArgs& z, int k0, double lam, c2<T>* col,
+                                                int stride) {
+    using C = c2<T>;
+    C d[KC];
+    T aa[KC], cc[KC];
+#pragma unroll
+    for (int i = 0; i < KC; ++i) d[i] = col[i * stride];
+    C dp{(T)0, (T)0};
+    T ap = (T)0, cp = (T)0;
+#pragma unroll
+    for (int i = 0; i < KC; ++i) {
+        const ZRow row = zrow(z, k0 + i, lam);
+        const double r = chunk_fwd<T>(i, row, ap, cp, aa[i], cc[i]);
+        d[i] = chunk_fwd_rhs<T>(i, row, r, d[i], dp);
+        dp = d[i];
+        ap = aa[i];
+        cp = cc[i];
+    }
+    if constexpr (KC >= 3) {
+        C db = d[KC - 2];
+        T ab = aa[KC - 2], cb = cc[KC - 2];
+#pragma unroll
+        for (int i = KC - 3; i >= 1; --i) {
+            db = chunk_bwd_rhs<T>(d[i], cc[i], db);
+            chunk_bwd<T>(aa[i], cc[i], ab, cb);
+        }
+        const T r0 = chunk_row0_pivot<T>(cc[0], ab);
+        d[0] = C{(d[0].x - cc[0] * db.x) * r0, (d[0].y - cc[0] * db.y) * r0};
+    }
+#pragma unroll
+    for (int i = 0; i < KC; ++i) col[i * stride] = d[i];
+}
+
+// Back substitution of one system's chunk: rows 0 and KC-1 hold x_first and
+// x_last, rows 1..KC-2 the forward-swept d_i; x_i = d_i - aa_i x_first -
+// cc_i x_{i+1}, from i = KC-2 down. Rows i >= nl are padding (x = 0).
+template <typename T, int KC>
+__device__ __forceinline__ void chunk_substitute(const ZArgs& z, int k0, int nl, double lam,
+                                                 c2<T>* col, int stride) {
+    using C = c2<T>;
+    if constexpr (KC >= 3) {
+        C d[KC];
+        T aa[KC], cc[KC];
+#pragma unroll
+        for (int i = 0; i < KC; ++i) d[i] = i < nl ? col[i * stride] : C{(T)0, (T)0};
+        T ap = (T)0, cp = (T)0;
+#pragma unroll
+        for (int i = 0; i < KC - 1; ++i) {
+            (void)chunk_fwd<T>(i, zrow(z, k0 + i, lam), ap, cp, aa[i], cc[i]);
+            ap = aa[i];
+            cp = cc[i];
+        }
+        const C xf = d[0];
+        C xn = d[KC - 1];
+#pragma unroll
+        for (int i = KC - 2; i >= 1; --i) {
+            xn = i < nl ? C{d[i].x - aa[i] * xf.x - cc[i] * xn.x, d[i].y - aa[i] * xf.y - cc[i] * xn.y}
+                        : C{(T)0, (T)0};
+            d[i] = xn;
+        }
+#pragma unroll
+        for (int i = 1; i < KC - 1; ++i)
+            if (i < nl) col[i * stride] = d[i];
+    }
+}
+
+// FFT of the tile's lines: in place for a compile-time length N, else the
+// runtime routine with the second buffer; returns the buffer with the result.
+template <typename T, int N, int KC, int DIR>
+__device__ __forceinline__ c2<T>* yz_fft(c2<T>* buf, int ny, int nlines, const Radices& rad,
+                                         const c2<T>* tw) {
+    if constexpr (N > 0) {
+        fft_inplace<N, 0, DIR, 1, KC>(buf, tw);
+        return buf;
+    } else {
+        return lds_fft<DIR>(buf, buf + KC * ny, ny, nlines, ny, rad, tw, ny);
+    }
+}
+
+// Stages the tile's lines (planes [k0, k0 + nl) of wavenumber m; rows past
+// nl read as 0) and the twiddles into LDS.
+template <typename T, int N, int KC>
+__device__ __forceinline__ void yz_load(const ZArgs& z, const c2<T>* __restrict__ base, size_t SP,
+                                        int nl, const c2<T>* __restrict__ tw_g, c2<T>* buf,
+                                        c2<T>* tw) {
+    using C = c2<T>;
+    const int ny = N ? N : z.ny;
+    for (int t = threadIdx.x; t < ny; t += 256) tw[t] = tw_g[t];
+    for (int e = threadIdx.x; e < KC * ny; e += 256) {
+        const int i = e / ny, n = e - i * ny;
+        buf[e] = i < nl ? base[(size_t)i * SP + n] : C{(T)0, (T)0};
+    }
+    __syncthreads();
+}
+
+// Forward y tile b = c mx + m (chunk c, wavenumber m): FFT along y of planes
+// [c KC, c KC + KC) and the local elimination of every system (m, n).
+// N = ny as a compile-time constant, or 0 for the runtime-length FFT.
+template <typename T, int N, int KC>
+__device__ __forceinline__ void yz_fwd_tile(const ZArgs& z, const Radices& rad,
+                                            c2<T>* __restrict__ spec, const c2<T>* __restrict__ tw_g,
+                                            int b, unsigned char* smem) {
+    using C = c2<T>;
+    const int ny = N ? N : z.ny;
+    C* buf = reinterpret_cast<C*>(smem);
+    C* tw = buf + (N ? 1 : 2) * KC * ny;  // exp(-2 pi i t / ny), t < ny
+    const int c = b / z.mx, m = b - c * z.mx;
+    const int k0 = c * KC;
+    const int nl = min(KC, z.nz - k0);
+    const size_t SP = (size_t)z.mx * ny;
+    C* base = spec + (size_t)k0 * SP + (size_t)m * ny;
+    yz_load<T, N, KC>(z, base, SP, nl, tw_g, buf, tw);
+    C* d = yz_fft<T, N, KC, -1>(buf, ny, KC, rad, tw);
+    for (int n = threadIdx.x; n < ny; n += 256) {
+        if (m == 0 && n == 0) continue;  // the (0,0) pair is solved apart
+        chunk_eliminate<T, KC>(z, k0, z.lamx[m] + z.lamy[n], d + n, ny);
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < nl * ny; e += 256) {
+        const int i = e / ny, n = e - i * ny;
+        base[(size_t)i * SP + n] = d[e];
+    }
+}
+
+// Inverse y tile b = c mx + m: x_first and x_last of every system sit in rows
+// 0 and KC-1 (written by the interface pass), the interior rows hold the
+// forward-swept d_i; back substitution, then the inverse FFT along y.
+template <typename T, int N, int KC>
+__device__ __forceinline__ void yz_inv_tile(const ZArgs& z, const Radices& rad,
+                                            c2<T>* __restrict__ spec, const c2<T>* __restrict__ tw_g,
+                                            int b, unsigned char* smem) {
+    using C = c2<T>;
+    const int ny = N ? N : z.ny;
+    C* buf = reinterpret_cast<C*>(smem);
+    C* tw = buf + (N ? 1 : 2) * KC * ny;
+    const int c = b / z.mx, m = b - c * z.mx;
+    const int k0 = c * KC;
+    const int nl = min(KC, z.nz - k0);
+    const size_t SP = (size_t)z.mx * ny;
+    C* base = spec + (size_t)k0 * SP + (size_t)m * ny;
+    yz_load<T, N, KC>(z, base, SP, nl, tw_g, buf, tw);
+    for (int n = threadIdx.x; n < ny; n += 256) {
+        if (m == 0 && n == 0) continue;
+        chunk_substitute<T, KC>(z, k0, nl, z.lamx[m] + z.lamy[n], buf + n, ny);
+    }
+    __syncthreads();
+    C* r = yz_fft<T, N, KC, +1>(buf, ny, nl, rad, tw);
+    for (int e = threadIdx.x; e < nl * ny; e += 256) {
+        const int i = e / ny, n = e - i * ny;
+        base[(size_t)i * SP + n] = r[e];
+    }
+}
+
+// Calls f with the compile-time chunk rows matching kc (4, 8 or 16).
+template <typename F>
+__device__ __forceinline__ void with_kc(int kc, F&& f) {
+    if (kc == 4)
+        f(std::integral_constant<int, 4>{});
+    else if (kc == 8)
+        f(std::integral_constant<int, 8>{});
+    else
+        f(std::integral_constant<int, 16>{});
+}
 
 __device__ __forceinline__ double wave_sum(double v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -101,251 +303,219 @@ __device__ __forceinline__ double wave_excl_scan(double v) {
     return inc - v;
 }
 
-// (0,0) column (contiguous in layout B), FP64, by one wave; lane l owns rows
-// [l C, (l+1) C). With r~_k = r_k - mean (mean = sum_k h_k r_k / lz, the
-// projection), the flux through face k is phi_{k-1} = sum_{j<k} h_j r~_j and
+// (0,0) column (entry k at col[k * stride]), FP64, as a tile of its own: the
+// block (any multiple of 64 threads) stages the real parts, h and g in LDS
+// (one global round trip), then one wave solves from there; lane l owns rows [l C, (l+1) C). With
+// r~_k = r_k - mean (mean = sum_k h_k r_k / lz, the projection), the flux
+// through face k is phi_{k-1} = sum_{j<k} h_j r~_j and
 // x_k = sum_{j<=k} g_j phi_{j-1} (x_0 = 0); then the gauge removes
 // sum_k h_k x_k / lz.
+inline size_t zero_mode_lds(int nz) { return ((size_t)3 * nz + 1) * sizeof(double); }
+
 template <typename TS>
-__device__ __forceinline__ void zero_mode_wave(const ZArgs& z, c2<TS>* colg) {
-    const int lane = threadIdx.x & 63;
+__device__ __forceinline__ void zero_mode_tile(const ZArgs& z, c2<TS>* col, size_t stride,
+                                               unsigned char* smem) {
+    double* r = reinterpret_cast<double*>(smem);
+    double* hh = r + z.nz;
+    double* gg = hh + z.nz;  // [nz + 1]
+    for (int k = threadIdx.x; k < z.nz; k += blockDim.x) {
+        r[k] = (double)col[(size_t)k * stride].x;
+        hh[k] = z.h[k];
+    }
+    for (int k = threadIdx.x; k <= z.nz; k += blockDim.x) gg[k] = z.g[k];
+    __syncthreads();
+    if (threadIdx.x >= 64) return;
+    const int lane = threadIdx.x;
     const int C = (z.nz + 63) / 64;
     const int k0 = min(lane * C, z.nz), k1 = min(k0 + C, z.nz);
     double s = 0.0;
-    for (int k = k0; k < k1; ++k) s += z.h[k] * (double)colg[k].x;
+    for (int k = k0; k < k1; ++k) s += hh[k] * r[k];
     s = wave_sum(s);
     const double mean = s / z.lz;
     if (lane == 0) *z.rhs_mean = s / z.nxny_lz;
     double t = 0.0;
-    for (int k = k0; k < k1; ++k) t += z.h[k] * ((double)colg[k].x - mean);
+    for (int k = k0; k < k1; ++k) t += hh[k] * (r[k] - mean);
     const double phi0 = wave_excl_scan(t);
     double u = 0.0, phi = phi0;
     for (int k = k0; k < k1; ++k) {
-        if (k > 0) u += z.g[k] * phi;
-        phi += z.h[k] * ((double)colg[k].x - mean);
+        if (k > 0) u += gg[k] * phi;
+        phi += hh[k] * (r[k] - mean);
     }
     const double x0 = wave_excl_scan(u);
     double hx = 0.0, x = x0;
     phi = phi0;
     for (int k = k0; k < k1; ++k) {
-        if (k > 0) x += z.g[k] * phi;
-        phi += z.h[k] * ((double)colg[k].x - mean);
-        hx += z.h[k] * x;
+        if (k > 0) x += gg[k] * phi;
+        phi += hh[k] * (r[k] - mean);
+        hx += hh[k] * x;
     }
     const double shift = wave_sum(hx) / z.lz;
-    // every lane has read its rows above; the writes below touch only them
     using T = decltype(c2<TS>::x);
     x = x0;
     phi = phi0;
     for (int k = k0; k < k1; ++k) {
-        if (k > 0) x += z.g[k] * phi;
-        phi += z.h[k] * ((double)colg[k].x - mean);
-        colg[k] = c2<TS>{(T)(x - shift), (T)0};
+        if (k > 0) x += gg[k] * phi;
+        phi += hh[k] * (r[k] - mean);
+        col[(size_t)k * stride] = c2<TS>{(T)(x - shift), (T)0};
     }
 }
 
-__device__ __forceinline__ double shfl_v(double v, int src) { return __shfl(v, src, 64); }
-__device__ __forceinline__ float shfl_v(float v, int src) { return __shfl(v, src, 64); }
+// plane of interface row r: first (even r) or last (odd r) row of chunk r/2
+__device__ __forceinline__ int ifc_plane(const ZArgs& z, int r) {
+    return (r >> 1) * z.kc + ((r & 1) ? z.kc - 1 : 0);
+}
 
-// LDS of a tridiagonal tile: columns staged with one pad entry per partition
-// (rows per lane L <= 8; longer chains read their rows from global memory)
+constexpr int IFC_SYS = 64;  // systems per interface tile (one wave)
+
+// Interface tile b: tile 0 is the (0,0) column; tile b >= 1 solves the
+// interface systems of pairs [(b-1) 64, b 64), one per lane of wave 0:
+//   d'_r = (D_r - A_r d'_{r-1}) / den_r,  x_r = d'_r - c'_r x_{r+1},
+// with A_r, c'_r and 1/den_r from the table. Rows go in segments of SEG held
+// in registers (each segment's loads issued together); d' of all but the
+// last segment waits in the spectrum for the backward sweep. A padded last
+// row (plane >= nz) is never stored.
 template <typename T>
-inline size_t tri_lds(int L) { return L <= 8 ? (size_t)256 * (L + 1) * sizeof(c2<T>) : 0; }
-
-// Tridiagonal tile b: systems [b * 256/P, (b+1) * 256/P), whose columns are
-// contiguous in layout B. For L <= 8 the block copies them to LDS with
-// coalesced 16-byte loads (partition p of a system at offset p (L+1)), each
-// lane then takes its L rows from there, and the solved columns go back the
-// same way. Tile 0's first wave also solves the (0,0) column.
-template <typename T, int L>
-__device__ __forceinline__ void tri_tile(const ZArgs& z, c2<T>* __restrict__ spec, int b,
+__device__ __forceinline__ void ifc_tile(const ZArgs& z, c2<T>* __restrict__ spec, int b,
                                          unsigned char* smem) {
     using C = c2<T>;
-    constexpr bool STAGE = L <= 8;
+    constexpr int SEG = sizeof(T) == 8 ? 16 : 32;
     const int S = z.mx * z.ny;
-    if (b == 0 && threadIdx.x < 64) zero_mode_wave<T>(z, spec);
-    const int P = z.P;
-    const int lane = threadIdx.x & 63;
-    const int p = lane & (P - 1);
-    const int gbase = lane - p;  // first lane of this system's group
-    const int sys_per_block = 256 / P;
-    const int s0 = b * sys_per_block;
-    const int sl = (int)(threadIdx.x / P);  // system within the tile
-    const int s = s0 + sl;
-    const bool active = (s < S) && (s != 0);
-    const int k0 = p * L;
-    C* colp = spec + (size_t)(active ? s : 0) * z.nz;
-    C* lds = reinterpret_cast<C*>(smem);
-    const int sstride = P * (L + 1);
-    const int cnt = min(sys_per_block, S - s0) * z.nz;
-    C d[L];
-    T aa[L], cc[L];
-    if constexpr (STAGE) {
-        const C* src = spec + (size_t)s0 * z.nz;
-        for (int e = threadIdx.x; e < cnt; e += 256) {
-            // (system, row) of element e; the float estimate is off by at most one
-            int q = (int)((float)e * z.rcp_nz);
-            int r = e - q * z.nz;
-            if (r < 0) { --q; r += z.nz; } else if (r >= z.nz) { ++q; r -= z.nz; }
-            lds[q * sstride + (r / L) * (L + 1) + (r % L)] = src[e];
-        }
-        __syncthreads();
-#pragma unroll
-        for (int i = 0; i < L; ++i) {
-            const int k = k0 + i;
-            d[i] = (active && k < z.nz) ? lds[sl * sstride + p * (L + 1) + i] : C{(T)0, (T)0};
-        }
-    } else {
-#pragma unroll
-        for (int i = 0; i < L; ++i) {
-            const int k = k0 + i;
-            d[i] = (active && k < z.nz) ? colp[k] : C{(T)0, (T)0};
-        }
-    }
-    double lam = 0.0;
-    if (active) {
-        const int m = s / z.ny;
-        lam = z.lamx[m] + z.lamy[s - m * z.ny];
-    }
-    // forward elimination: rows end as aa_i x_first + x_i + cc_i x_{i+1} = d_i
-    // (row 0 keeps its coupling aa_0 to the previous partition's last unknown)
-#pragma unroll
-    for (int i = 0; i < L; ++i) {
-        const int k = k0 + i;
-        double a = 0.0, bb = 1.0, c = 0.0;
-        if (active && k < z.nz) {
-            a = z.za[k];
-            bb = z.zb[k] + lam;
-            c = z.zc[k];
-        }
-        if (i < 2) {
-            const double r = 1.0 / bb;
-            aa[i] = (T)(a * r);
-            cc[i] = (T)(c * r);
-            d[i] = C{(T)(d[i].x * r), (T)(d[i].y * r)};
-        } else {
-            const double r = 1.0 / (bb - a * (double)cc[i - 1]);
-            aa[i] = (T)(-a * (double)aa[i - 1] * r);
-            cc[i] = (T)(c * r);
-            d[i] = C{(T)((d[i].x - a * d[i - 1].x) * r), (T)((d[i].y - a * d[i - 1].y) * r)};
-        }
-    }
-    // backward: rows 1..L-2 end as aa_i x_first + x_i + cc_i x_last = d_i
-#pragma unroll
-    for (int i = L - 3; i >= 1; --i) {
-        d[i] = C{d[i].x - cc[i] * d[i + 1].x, d[i].y - cc[i] * d[i + 1].y};
-        aa[i] = aa[i] - cc[i] * aa[i + 1];
-        cc[i] = -cc[i] * cc[i + 1];
-    }
-    if (L >= 3) {
-        const T r = (T)1 / ((T)1 - cc[0] * aa[1]);
-        d[0] = C{(d[0].x - cc[0] * d[1].x) * r, (d[0].y - cc[0] * d[1].y) * r};
-        aa[0] = aa[0] * r;
-        cc[0] = -cc[0] * cc[1] * r;
-    }
-    // interface system of 2P rows, ordered (first_0, last_0, first_1, ...):
-    //   A_i x_{i-1} + B_i x_i + C_i x_{i+1} = D_i, solved by cyclic reduction.
-    T A[2] = {aa[0], aa[L - 1]};
-    T B[2] = {(T)1, (T)1};
-    T Cc[2] = {cc[0], cc[L - 1]};
-    C D[2] = {d[0], d[L - 1]};
-    const int nrow = 2 * P;
-    for (int st = 1; st < nrow; st <<= 1) {
-        T nA[2], nB[2], nC[2];
-        C nD[2];
-#pragma unroll
-        for (int e = 0; e < 2; ++e) {
-            const int i = 2 * p + e;
-            const int jl = i - st, jr = i + st;
-            const int sl = jl & 1, sr = jr & 1;  // uniform over the wave
-            const int ll = (gbase + (jl >> 1)) & 63, lr = (gbase + (jr >> 1)) & 63;
-            // values of rows jl and jr (identity rows outside 0..2P-1)
-            const T la = shfl_v(sl ? A[1] : A[0], ll), lb = shfl_v(sl ? B[1] : B[0], ll);
-            const T lc = shfl_v(sl ? Cc[1] : Cc[0], ll);
-            const T ldx = shfl_v(sl ? D[1].x : D[0].x, ll), ldy = shfl_v(sl ? D[1].y : D[0].y, ll);
-            const T ra = shfl_v(sr ? A[1] : A[0], lr), rb = shfl_v(sr ? B[1] : B[0], lr);
-            const T rc = shfl_v(sr ? Cc[1] : Cc[0], lr);
-            const T rdx = shfl_v(sr ? D[1].x : D[0].x, lr), rdy = shfl_v(sr ? D[1].y : D[0].y, lr);
-            const bool hl = jl >= 0, hr = jr < nrow;
-            const T al = hl ? -A[e] / lb : (T)0;
-            const T ar = hr ? -Cc[e] / rb : (T)0;
-            nA[e] = hl ? al * la : (T)0;
-            nC[e] = hr ? ar * rc : (T)0;
-            nB[e] = B[e] + (hl ? al * lc : (T)0) + (hr ? ar * ra : (T)0);
-            nD[e] = C{D[e].x + (hl ? al * ldx : (T)0) + (hr ? ar * rdx : (T)0),
-                      D[e].y + (hl ? al * ldy : (T)0) + (hr ? ar * rdy : (T)0)};
-        }
-#pragma unroll
-        for (int e = 0; e < 2; ++e) {
-            A[e] = nA[e];
-            B[e] = nB[e];
-            Cc[e] = nC[e];
-            D[e] = nD[e];
-        }
-    }
-    const C xf = C{D[0].x / B[0], D[0].y / B[0]};
-    const C xl = C{D[1].x / B[1], D[1].y / B[1]};
-#pragma unroll
-    for (int i = 1; i < L - 1; ++i)
-        d[i] = C{d[i].x - aa[i] * xf.x - cc[i] * xl.x, d[i].y - aa[i] * xf.y - cc[i] * xl.y};
-    d[0] = xf;
-    d[L - 1] = xl;
-    if constexpr (STAGE) {
-        // each lane rewrites only the slots it read; then the block stores the
-        // tile coalesced, leaving the (0,0) column to the zero-mode wave
-        if (active) {
-#pragma unroll
-            for (int i = 0; i < L; ++i)
-                if (k0 + i < z.nz) lds[sl * sstride + p * (L + 1) + i] = d[i];
-        }
-        __syncthreads();
-        C* dst = spec + (size_t)s0 * z.nz;
-        for (int e = threadIdx.x; e < cnt; e += 256) {
-            int q = (int)((float)e * z.rcp_nz);
-            int r = e - q * z.nz;
-            if (r < 0) { --q; r += z.nz; } else if (r >= z.nz) { ++q; r -= z.nz; }
-            if (s0 + q != 0) dst[e] = lds[q * sstride + (r / L) * (L + 1) + (r % L)];
-        }
-    } else if (active) {
-#pragma unroll
-        for (int i = 0; i < L; ++i) {
-            const int k = k0 + i;
-            if (k < z.nz) colp[k] = d[i];
-        }
-    }
-}
-
-// Rows per lane L and lanes per system P for a column of nz rows, starting
-// from the preferred L (8 unless tuned): short chains keep the serial
-// elimination short and give many waves; L grows only when 64 lanes per
-// system would not cover the column.
-inline void tri_shape(int nz, int& L, int& P, int prefer = 8) {
-    if (nz <= 8 && prefer >= 8) {
-        P = 1;
-        L = 2;
-        while (L < nz) L *= 2;
+    const size_t SP = (size_t)S;
+    if (b == 0) {
+        zero_mode_tile<T>(z, spec, SP, smem);
         return;
     }
-    for (L = prefer; L <= 32; L *= 2) {
-        P = 1;
-        while (P * L < nz) P *= 2;
-        if (P <= 64) return;
+    if (threadIdx.x >= IFC_SYS) return;
+    const int s = (b - 1) * IFC_SYS + (int)threadIdx.x;
+    if (s >= S || s == 0) return;
+    const int R = 2 * z.nc;
+    const int nseg = (R + SEG - 1) / SEG;
+    // 32-bit element offsets (every index here is below nx ny nz < 2^31)
+    const T* tA = reinterpret_cast<const T*>(z.tab);
+    const T* tC = tA + (size_t)R * S;
+    const T* tI = tC + (size_t)R * S;
+    const unsigned us = (unsigned)s, uS = (unsigned)S;
+    auto row_off = [&](int r) { return (unsigned)r * uS + us; };
+    auto plane_off = [&](int r) { return (unsigned)ifc_plane(z, r) * uS + us; };
+    C d[SEG];
+    T cp[SEG];
+    C dp{(T)0, (T)0};
+    int r0 = 0;
+    for (int sg = 0; sg < nseg; ++sg) {
+        r0 = sg * SEG;
+        const bool last = sg == nseg - 1;
+        T A[SEG], I[SEG];
+#pragma unroll
+        for (int j = 0; j < SEG; ++j) {
+            const int r = r0 + j;
+            A[j] = (T)0;
+            I[j] = (T)0;
+            cp[j] = (T)0;
+            d[j] = C{(T)0, (T)0};
+            if (r < R) {
+                A[j] = tA[row_off(r)];
+                I[j] = tI[row_off(r)];
+                if (last) cp[j] = tC[row_off(r)];
+                if (ifc_plane(z, r) < z.nz) d[j] = spec[plane_off(r)];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < SEG; ++j) {
+            if (r0 + j < R) {
+                dp = C{(d[j].x - A[j] * dp.x) * I[j], (d[j].y - A[j] * dp.y) * I[j]};
+                d[j] = dp;
+                if (!last) spec[plane_off(r0 + j)] = dp;
+            }
+        }
     }
-    L = 32;
-    P = 64;
+    // backward: the last segment from registers
+    C x{(T)0, (T)0};
+#pragma unroll
+    for (int j = SEG - 1; j >= 0; --j) {
+        const int r = r0 + j;
+        if (r < R) {
+            x = r == R - 1 ? d[j] : C{d[j].x - cp[j] * x.x, d[j].y - cp[j] * x.y};
+            if (ifc_plane(z, r) < z.nz) spec[plane_off(r)] = x;
+        }
+    }
+    // earlier segments (all rows below R-1, so real planes) from the spectrum
+    for (int sg = nseg - 2; sg >= 0; --sg) {
+        const int q0 = sg * SEG;
+#pragma unroll
+        for (int j = 0; j < SEG; ++j) {
+            cp[j] = tC[row_off(q0 + j)];
+            d[j] = spec[plane_off(q0 + j)];
+        }
+#pragma unroll
+        for (int j = SEG - 1; j >= 0; --j) {
+            x = C{d[j].x - cp[j] * x.x, d[j].y - cp[j] * x.y};
+            spec[plane_off(q0 + j)] = x;
+        }
+    }
 }
 
-inline void tri_shape(const Plan& p, int& L, int& P) { tri_shape(p.nz, L, P, p.lp.tri_L); }
+// Interface factors of pair s (plan time; thread per pair, kc <= 64 rows of
+// scratch per thread in LDS at [i][thread]): the coefficients (A, C) of the
+// first and last row of every chunk, from the same sweeps as the y tiles,
+// then the Thomas factors c'_r = C_r / den_r, 1/den_r with
+// den_r = 1 - A_r c'_{r-1} (den_0 = 1).
+template <typename T>
+__device__ __forceinline__ void ifc_table_pair(const ZArgs& z, int s, T* tab, c2<T>* scratch,
+                                               int sstride) {
+    using C = c2<T>;
+    const int S = z.mx * z.ny;
+    const int R = 2 * z.nc;
+    T* tA = tab;
+    T* tC = tab + (size_t)R * S;
+    T* tI = tC + (size_t)R * S;
+    const int m = s / z.ny, n = s - m * z.ny;
+    const double lam = z.lamx[m] + z.lamy[n];
+    const int kc = z.kc;
+    T cprev = (T)0;
+    for (int c = 0; c < z.nc; ++c) {
+        const int k0 = c * kc;
+        T aa = (T)0, cc = (T)0;
+        for (int i = 0; i < kc; ++i) {
+            const ZRow row = zrow(z, k0 + i, lam);
+            T na, ncc;
+            (void)chunk_fwd<T>(i, row, aa, cc, na, ncc);
+            scratch[i * sstride] = C{na, ncc};
+            aa = na;
+            cc = ncc;
+        }
+        const C w0 = scratch[0];
+        const C wl = scratch[(kc - 1) * sstride];
+        T A0 = w0.x, C0 = w0.y;
+        if (kc >= 3) {
+            T ab = scratch[(kc - 2) * sstride].x, cb = scratch[(kc - 2) * sstride].y;
+            for (int i = kc - 3; i >= 1; --i) {
+                const C wi = scratch[i * sstride];
+                chunk_bwd<T>(wi.x, wi.y, ab, cb);
+            }
+            const T r0 = chunk_row0_pivot<T>(w0.y, ab);
+            A0 = w0.x * r0;
+            C0 = -w0.y * cb * r0;
+        }
+        const T rowA[2] = {A0, wl.x};
+        const T rowC[2] = {C0, wl.y};
+        for (int e = 0; e < 2; ++e) {
+            const int r = 2 * c + e;
+            const T inv = r == 0 ? (T)1 : (T)1 / ((T)1 - rowA[e] * cprev);
+            cprev = rowC[e] * inv;
+            tA[(size_t)r * S + s] = rowA[e];
+            tC[(size_t)r * S + s] = cprev;
+            tI[(size_t)r * S + s] = inv;
+        }
+    }
+}
 
 inline ZArgs make_zargs(const Plan& p, double* mean_out) {
     ZArgs z;
     z.nz = p.nz;
     z.mx = p.mx;
     z.ny = p.ny;
-    int L = 8, P = 1;
-    tri_shape(p, L, P);
-    z.P = P;
-    z.rcp_nz = 1.0f / (float)p.nz;
+    z.kc = p.lp.kc;
+    z.nc = (p.nz + p.lp.kc - 1) / p.lp.kc;
     z.lz = p.grid.lz;
     z.nxny_lz = (double)p.nx * p.ny * p.grid.lz;
     z.za = p.t.za;
@@ -356,16 +526,12 @@ inline ZArgs make_zargs(const Plan& p, double* mean_out) {
     z.h = p.t.h;
     z.g = p.t.g;
     z.rhs_mean = mean_out;
+    z.tab = p.ifc_tab;
     return z;
 }
 
-inline int tri_tiles(const Plan& p) {
-    int L = 8, P = 1;
-    tri_shape(p, L, P);
-    const int spb = 256 / P;
-    return (p.mx * p.ny + spb - 1) / spb;
-}
-
-inline int fft_y_tiles(const Plan& p) { return p.mx * ((p.nz + p.lp.lby - 1) / p.lp.lby); }
+inline int yz_tiles(const Plan& p) { return p.mx * ((p.nz + p.lp.kc - 1) / p.lp.kc); }
+inline int ifc_tiles(const Plan& p) { return 1 + (p.mx * p.ny + IFC_SYS - 1) / IFC_SYS; }
+inline size_t ifc_lds(const Plan& p) { return zero_mode_lds(p.nz); }
 
 }  // namespace psv

@@ -7,6 +7,7 @@
 #include <sstream>
 
 #include "pass_x.hpp"
+#include "pass_yz.hpp"
 
 namespace psv {
 
@@ -117,12 +118,6 @@ static T* upload(const std::vector<T>& v) {
     return d;
 }
 
-static int pick_lines(int ny, size_t bytes_per_line, size_t budget, int cap) {
-    int lb = 1;
-    while (lb * 2 <= cap && ny % (lb * 2) == 0 && (size_t)(lb * 2) * bytes_per_line <= budget) lb *= 2;
-    return lb;
-}
-
 void plan_init(Plan& p, const psv_grid& g, const psv_opts& o, bool alloc_ws) {
     p.grid = g;
     p.opts = o;
@@ -192,14 +187,22 @@ void plan_init(Plan& p, const psv_grid& g, const psv_opts& o, bool alloc_ws) {
     int lds_max = 0;
     PSV_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, p.device));
     const size_t budget = (size_t)std::min(lds_max, 64 * 1024) - 2048;
-    // (the twiddle table of each direction also lives in LDS)
-    const size_t by = budget - (size_t)p.ny * sizeof(double2);
     p.lp.lbx = 1;
     while (p.lp.lbx * 2 <= 16 && p.ny % (p.lp.lbx * 2) == 0 && x_lds_max(p.nx, p.lp.lbx * 2) <= budget)
         p.lp.lbx *= 2;
-    p.lp.lby = pick_lines(1 << 20, (size_t)2 * (p.ny + 1) * sizeof(double2), by, 16);
-    if (x_lds_max(p.nx, p.lp.lbx) > budget || (size_t)p.lp.lby * 2 * (p.ny + 1) * sizeof(double2) > by)
+    if (x_lds_max(p.nx, p.lp.lbx) > budget)
         fail(PSV_ERR_UNSUPPORTED_SIZE, "line length exceeds the LDS budget");
+    // chunk rows of the z partition: the largest of 16, 8, 4 whose y tile
+    // takes at most 48 KiB of LDS (three blocks per CU), else the largest
+    // that fits a block at all
+    const size_t csz = p.opts.precision == PSV_MIXED ? sizeof(float2) : sizeof(double2);
+    int kc = 0;
+    for (int c : {16, 8, 4})
+        if (!kc && yz_lds(p.ny, c, csz) <= 48 * 1024) kc = c;
+    if (!kc)
+        for (int c : {16, 8, 4})
+            if (!kc && kc_fits(p, c)) kc = c;
+    if (!kc) fail(PSV_ERR_UNSUPPORTED_SIZE, "y lines exceed the LDS of a block");
 
     p.t.twx64 = upload(tx64);
     p.t.twx32 = upload(tx32);
@@ -216,6 +219,7 @@ void plan_init(Plan& p, const psv_grid& g, const psv_opts& o, bool alloc_ws) {
     p.t.g = upload(p.g);
     p.t.vol = upload(vol);
     p.t.inv_vol = upload(inv_vol);
+    plan_set_kc(p, kc);
     // per-block partial sums: 2 per forward-x block, or the reductions' 1.5 * 1024
     // two per forward-x block at any lines-per-block (the autotuner may pick 1)
     p.n_partials = std::max(8192, 2 * p.ny * p.nz + 64);
@@ -227,10 +231,9 @@ void plan_init(Plan& p, const psv_grid& g, const psv_opts& o, bool alloc_ws) {
     PSV_HIP(hipHostMalloc(&p.host_scal, S_NSCAL * sizeof(double)));
     PSV_HIP(hipHostMalloc(&p.host_flags, F_NFLAG * sizeof(int)));
     const size_t nspec = p.nspec(), ncell = p.ncell();
-    p.ws_bytes = 2 * nspec * sizeof(double2) + 2 * ncell * sizeof(double);
+    p.ws_bytes = nspec * sizeof(double2) + 2 * ncell * sizeof(double);
     if (alloc_ws) {
         PSV_HIP(hipMalloc(&p.spec, nspec * sizeof(double2)));
-        PSV_HIP(hipMalloc(&p.spec_t, nspec * sizeof(double2)));
         PSV_HIP(hipMalloc(&p.r_ws, 2 * ncell * sizeof(double)));
         p.own_ws = true;
         if (p.opts.autotune >= 1) autotune_plan(p);
@@ -240,12 +243,11 @@ void plan_init(Plan& p, const psv_grid& g, const psv_opts& o, bool alloc_ws) {
 void plan_free(Plan& p) {
     void* ptrs[] = {p.t.twx64, p.t.twx32, p.t.twy64, p.t.twy32, p.t.lamx, p.t.lamy, p.t.za,
                     p.t.zb, p.t.zc, p.t.inv_h, p.t.inv_g, p.t.h, p.t.g, p.t.vol, p.t.inv_vol,
-                    p.partials, p.scal, p.flags};
+                    p.partials, p.scal, p.flags, p.ifc_tab};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     if (p.own_ws) {
         if (p.spec) (void)hipFree(p.spec);
-        if (p.spec_t) (void)hipFree(p.spec_t);
         if (p.r_ws) (void)hipFree(p.r_ws);
     }
     if (p.host_scal) (void)hipHostFree(p.host_scal);
