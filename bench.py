@@ -139,7 +139,7 @@ def trace_name(rocprof_name):
         mode = n.split("k_inv_x<")[1].split(",")[2].strip()
         return f"inv_x_{['store', 'add', 'scale'][int(mode)]}_{prec}"
     if "k_yz<" in n:
-        inv = n.split("k_yz<")[1].split(",")[2].split(">")[0].strip()
+        inv = n.split("k_yz<")[1].split(",")[3].split(">")[0].strip()
         return f"yz_{'inv' if inv == 'true' else 'fwd'}_{prec}"
     if "k_ifc<" in n:
         return f"z_interface_{prec}"
@@ -166,13 +166,16 @@ def ingest_pmc(fetch_csv, write_csv, workload, command):
         counts = collections.defaultdict(int)
         for r in csv.DictReader(open(path)):
             v = float(r["Counter_Value"]) * 1024.0
-            if "copyBuffer" in r["Kernel_Name"] and int(r["Grid_Size"]) >= 65536:
+            if "copyBuffer" in r["Kernel_Name"]:
                 probe.append(v)
             name = trace_name(r["Kernel_Name"])
             if name:
                 sums[name] += v
                 if "k_min_final" not in r["Kernel_Name"]:
                     counts[name] += 1
+        # the probe's three 256 MiB copies are the largest copies of the run
+        # (input uploads are staged in much smaller copy dispatches)
+        probe = sorted(probe)[-3:]
         scale = COPY_PROBE_BYTES / (sum(probe) / len(probe))
         out[f"{key}_scale"] = scale
         for name in sums:
