@@ -83,6 +83,9 @@ typedef struct {
     int32_t autotune;        /* 0: built-in launch shapes; 1: time candidates at plan creation */
     int32_t batch_executor;  /* batches: 0 default (per-pass launches), 1 per-pass launches,
                                 2 one persistent launch over the task queue */
+    int32_t chunk_rows;      /* rows per chunk of the wall-normal partition (planes per y
+                                tile): 0 automatic (tuned when autotune = 1), else 4, 8
+                                or 16 (PSV_ERR_UNSUPPORTED_SIZE if its tile does not fit) */
 } psv_opts;
 
 typedef struct {

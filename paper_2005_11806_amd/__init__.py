@@ -108,7 +108,7 @@ class Plan:
     """
 
     def __init__(self, grid: Grid, precision="fp64", method="method1", tol=1e-10,
-                 max_refine=4, check_inputs=False, autotune=0):
+                 max_refine=4, check_inputs=False, autotune=0, chunk_rows=0):
         self.grid = grid
         self.precision = precision
         self.method = method
@@ -120,6 +120,7 @@ class Plan:
         o.max_refine = int(max_refine)
         o.check_inputs = int(bool(check_inputs))
         o.autotune = int(autotune)
+        o.chunk_rows = int(chunk_rows)
         g, _keep = grid._c()
         h = C.c_void_p()
         check(lib().psv_plan_create(C.byref(g), C.byref(o), C.byref(h)))
@@ -236,7 +237,7 @@ class Batch:
     _EXEC = {"default": 0, "passes": 1, "persistent": 2}
 
     def __init__(self, grids, precision="mixed", method="method1", tol=1e-10, max_refine=4,
-                 executor="default"):
+                 executor="default", chunk_rows=0):
         self.grids = list(grids)
         n = len(self.grids)
         arr = (_abi.psv_grid * n)()
@@ -252,6 +253,7 @@ class Batch:
         o.tol = float(tol)
         o.max_refine = int(max_refine)
         o.batch_executor = self._EXEC[executor]
+        o.chunk_rows = int(chunk_rows)
         h = C.c_void_p()
         check(lib().psv_batch_create(n, arr, C.byref(o), C.byref(h)))
         self._h = h

@@ -34,6 +34,7 @@ std::string tune_key(const Plan& p) {
     os << prop.gcnArchName << ":" << p.nx << "x" << p.ny << "x" << p.nz << ":"
        << (p.opts.precision == PSV_MIXED ? "mixed" : "fp64") << ":"
        << (p.opts.method == PSV_SPLIT_RHO0 ? "method1" : "const");
+    if (p.opts.chunk_rows) os << ":kc" << p.opts.chunk_rows;
     return os.str();
 }
 
@@ -112,10 +113,11 @@ void autotune_plan(Plan& p) {
     load_cache();
     const std::string key = tune_key(p);
     auto it = g_cache.find(key);
+    const bool kc_fixed = p.opts.chunk_rows != 0;
     if (it != g_cache.end()) {
         if (fits_x(p, it->second.lbx) && kc_fits(p, it->second.kc)) {
             p.lp.lbx = it->second.lbx;
-            if (it->second.kc != p.lp.kc) plan_set_kc(p, it->second.kc);
+            if (!kc_fixed && it->second.kc != p.lp.kc) plan_set_kc(p, it->second.kc);
             return;
         }
     }
@@ -149,7 +151,7 @@ void autotune_plan(Plan& p) {
     p.lp.lbx = best.lbx;
     tbest = 1e30f;
     for (int kc : {4, 8, 16}) {
-        if (!kc_fits(p, kc) || kc > 2 * p.nz) continue;
+        if (!kc_fits(p, kc) || kc > 2 * p.nz || (kc_fixed && kc != def.kc)) continue;
         plan_set_kc(p, kc);
         // the z solve keeps the spectrum finite on repeated application
         launch_fwd_x(p, fp32, a, s);

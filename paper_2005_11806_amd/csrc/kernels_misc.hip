@@ -20,15 +20,16 @@ __global__ void __launch_bounds__(RB) k_min_partial(const double* __restrict__ x
     int bi = 0x7fffffff;
     // pairs (16-byte loads), four in flight, visited in increasing index
     // order so that a strict '<' keeps the first minimum
+    constexpr int U = 4;
     const double2* x2 = reinterpret_cast<const double2*>(x);
     const size_t n2 = n / 2, stride = (size_t)gridDim.x * RB;
     size_t c = (size_t)blockIdx.x * RB + threadIdx.x;
-    for (; c + 3 * stride < n2; c += 4 * stride) {
-        double2 v[4];
+    for (; c + (U - 1) * stride < n2; c += U * stride) {
+        double2 v[U];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) v[u] = x2[c + u * stride];
+        for (int u = 0; u < U; ++u) v[u] = x2[c + u * stride];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < U; ++u) {
             if (v[u].x < best) { best = v[u].x; bi = (int)(2 * (c + u * stride)); }
             if (v[u].y < best) { best = v[u].y; bi = (int)(2 * (c + u * stride) + 1); }
         }
@@ -133,33 +134,50 @@ __device__ __forceinline__ void cell_coords(size_t c, const Geo& g, int& i, int&
     k = (int)(q / g.ny);
 }
 
-// res = r - mean - L p ; partial sums of res^2 and (r - mean)^2
+// res = r - mean - L p ; partial sums of res^2 and (r - mean)^2. One thread
+// per pair of cells (2q, 2q+1) of an x-line (nx is even), 16-byte loads,
+// 32-bit index arithmetic (every index is below nx ny nz < 2^31).
 __global__ void __launch_bounds__(RB) k_residual(Geo g, const double* __restrict__ r,
                                                  const double* __restrict__ p,
                                                  const double* mean_p, double* partials) {
     __shared__ double sh[16];
-    const size_t n = (size_t)g.nx * g.ny * g.nz;
-    const size_t plane = (size_t)g.nx * g.ny;
+    const unsigned M = (unsigned)g.nx / 2u;  // pairs per line
+    const unsigned npair = M * (unsigned)g.ny * (unsigned)g.nz;
+    const unsigned pl2 = M * (unsigned)g.ny;  // pairs per plane
+    const double2* p2 = reinterpret_cast<const double2*>(p);
+    const double2* r2 = reinterpret_cast<const double2*>(r);
     const double mean = *mean_p;
+    const double idx2 = g.inv_dx * g.inv_dx, idy2 = g.inv_dy * g.inv_dy;
     double s1 = 0.0, s2 = 0.0;
-    for (size_t c = (size_t)blockIdx.x * RB + threadIdx.x; c < n; c += (size_t)gridDim.x * RB) {
-        int i, j, k;
-        cell_coords(c, g, i, j, k);
-        const size_t row = c - i;
-        const double pc = p[c];
-        const double pe = p[row + (i + 1 == g.nx ? 0 : i + 1)];
-        const double pw = p[row + (i == 0 ? g.nx - 1 : i - 1)];
-        const double pn = p[c - (size_t)j * g.nx + (size_t)(j + 1 == g.ny ? 0 : j + 1) * g.nx];
-        const double ps = p[c - (size_t)j * g.nx + (size_t)(j == 0 ? g.ny - 1 : j - 1) * g.nx];
-        double lp = ((pe - pc) - (pc - pw)) * (g.inv_dx * g.inv_dx) +
-                    ((pn - pc) - (pc - ps)) * (g.inv_dy * g.inv_dy);
-        const double ft = (k + 1 < g.nz) ? (p[c + plane] - pc) * g.inv_g[k + 1] : 0.0;
-        const double fb = (k > 0) ? (pc - p[c - plane]) * g.inv_g[k] : 0.0;
-        lp += (ft - fb) * g.inv_h[k];
-        const double rp = r[c] - mean;
-        const double res = rp - lp;
-        s1 += res * res;
-        s2 += rp * rp;
+    for (unsigned q = blockIdx.x * RB + threadIdx.x; q < npair; q += gridDim.x * RB) {
+        const unsigned line = q / M, n = q - line * M;
+        const unsigned k = line / (unsigned)g.ny, j = line - k * (unsigned)g.ny;
+        const unsigned row = q - n;  // first pair of the line
+        const double2 pc = p2[q];
+        const double pw = p2[row + (n == 0 ? M - 1 : n - 1)].y;
+        const double pe = p2[row + (n + 1 == M ? 0 : n + 1)].x;
+        const double2 pn = p2[j + 1 == (unsigned)g.ny ? q - j * M : q + M];
+        const double2 ps = p2[j == 0 ? q + ((unsigned)g.ny - 1) * M : q - M];
+        double l0 = ((pc.y - pc.x) - (pc.x - pw)) * idx2 + ((pn.x - pc.x) - (pc.x - ps.x)) * idy2;
+        double l1 = ((pe - pc.y) - (pc.y - pc.x)) * idx2 + ((pn.y - pc.y) - (pc.y - ps.y)) * idy2;
+        double ft0 = 0.0, ft1 = 0.0, fb0 = 0.0, fb1 = 0.0;  // wall fluxes are zero
+        if (k + 1 < (unsigned)g.nz) {
+            const double2 pt = p2[q + pl2];
+            ft0 = (pt.x - pc.x) * g.inv_g[k + 1];
+            ft1 = (pt.y - pc.y) * g.inv_g[k + 1];
+        }
+        if (k > 0) {
+            const double2 pb = p2[q - pl2];
+            fb0 = (pc.x - pb.x) * g.inv_g[k];
+            fb1 = (pc.y - pb.y) * g.inv_g[k];
+        }
+        l0 += (ft0 - fb0) * g.inv_h[k];
+        l1 += (ft1 - fb1) * g.inv_h[k];
+        const double2 rv = r2[q];
+        const double rp0 = rv.x - mean, rp1 = rv.y - mean;
+        const double e0 = rp0 - l0, e1 = rp1 - l1;
+        s1 += e0 * e0 + e1 * e1;
+        s2 += rp0 * rp0 + rp1 * rp1;
     }
     const double a = block_sum(s1, sh);
     __syncthreads();

@@ -105,20 +105,6 @@ __device__ __forceinline__ void fwd_x_tile(const XGeom& g, const Stencil& st, co
     double2* rt = pt + (lb + 2) * M;                 // staged rho rows (Method I)
     for (int t = threadIdx.x; t < 2 * M; t += 256) tw[t] = tw_g[t];
     const size_t plane = (size_t)nx * g.ny;
-    if (MODE != FWD_CONST) {
-        const double2* p2 = reinterpret_cast<const double2*>(a.pprev);
-        const double2* r2g = reinterpret_cast<const double2*>(a.rho);
-        for (int t = threadIdx.x; t < (lb + 2) * M; t += 256) {
-            const int rr = t / M;
-            const int q = t - rr * M;
-            int j = j0 - 1 + rr;
-            j = (j < 0) ? j + g.ny : (j >= g.ny ? j - g.ny : j);
-            const size_t src = ((size_t)k * g.ny + j) * M + q;
-            pt[t] = p2[src];
-            if (MODE == FWD_METHOD1) rt[t] = r2g[src];
-        }
-        __syncthreads();
-    }
 
     const double rho0 = (MODE == FWD_METHOD1) ? *a.rho0 : 0.0;
     const double two_r0 = 2.0 * rho0;
@@ -129,67 +115,114 @@ __device__ __forceinline__ void fwd_x_tile(const XGeom& g, const Stencil& st, co
     const double igt = has_t ? st.inv_g[k + 1] : 0.0, igb = has_b ? st.inv_g[k] : 0.0;
     const double ih = st.inv_h[k];
     double res2 = 0.0, r2 = 0.0, rsum = 0.0;
-    // one thread per pair of cells (2n, 2n+1): exactly the packed input
-    // z_n = r_{2n} + i r_{2n+1} of the half-length transform
-    for (int t = threadIdx.x; t < lb * M; t += 256) {
+    // One thread per pair of cells (2n, 2n+1): exactly the packed input
+    // z_n = r_{2n} + i r_{2n+1} of the half-length transform. The global
+    // operands of a thread's next PF pairs (f or r_in, and p, rho on the
+    // planes k +- 1) are loaded into registers together; the first batch is
+    // issued before the row staging, so the two loads overlap.
+    struct Pre {
+        double2 f, ptz, pbz, rtz, rbz;
+    };
+    constexpr int PF = 2;
+    const int npair = lb * M;
+    const double2* fg = reinterpret_cast<const double2*>(MODE == FWD_RESID ? a.r_in : a.f);
+    const double2* pg = reinterpret_cast<const double2*>(a.pprev);
+    const double2* rg = reinterpret_cast<const double2*>(a.rho);
+    auto pair_index = [&](int t) {
         const int line = t / M;
-        const int n = t - line * M;
-        const size_t c2 = (((size_t)k * g.ny + j0 + line) * nx) / 2 + n;  // double2 index
-        double v0, v1;
-        if (MODE == FWD_CONST) {
-            const double2 fv = reinterpret_cast<const double2*>(a.f)[c2];
-            v0 = fv.x * sc;
-            v1 = fv.y * sc;
-        } else {
-            const double2* P = pt + (line + 1) * M;
-            const double2 pc = P[n], pn = P[n + M], ps = P[n - M];
-            const double pw = P[n == 0 ? M - 1 : n - 1].y, pe = P[n + 1 == M ? 0 : n + 1].x;
-            double2 ptz{0.0, 0.0}, pbz{0.0, 0.0};
-            const double2* pg = reinterpret_cast<const double2*>(a.pprev);
-            if (has_t) ptz = pg[c2 + plane / 2];
-            if (has_b) pbz = pg[c2 - plane / 2];
-            if (MODE == FWD_METHOD1) {
-                const double2* R = rt + (line + 1) * M;
-                const double2 rc = R[n], rn = R[n + M], rs = R[n - M];
-                const double rw = R[n == 0 ? M - 1 : n - 1].y, re = R[n + 1 == M ? 0 : n + 1].x;
-                const double2* rg = reinterpret_cast<const double2*>(a.rho);
-                double2 rtz{1.0, 1.0}, rbz{1.0, 1.0};
-                if (has_t) rtz = rg[c2 + plane / 2];
-                if (has_b) rbz = rg[c2 - plane / 2];
-                const double2 fv = reinterpret_cast<const double2*>(a.f)[c2];
-                // x faces: west of 2n, between the pair, east of 2n+1
-                const double fw = bflux(rw, rc.x, pw, pc.x, two_r0);
-                const double fm = bflux(rc.x, rc.y, pc.x, pc.y, two_r0);
-                const double fe = bflux(rc.y, re, pc.y, pe, two_r0);
-                double d0 = (fm - fw) * idx2, d1 = (fe - fm) * idx2;
-                d0 += (bflux(rc.x, rn.x, pc.x, pn.x, two_r0) - bflux(rs.x, rc.x, ps.x, pc.x, two_r0)) * idy2;
-                d1 += (bflux(rc.y, rn.y, pc.y, pn.y, two_r0) - bflux(rs.y, rc.y, ps.y, pc.y, two_r0)) * idy2;
-                const double t0 = has_t ? bflux(rc.x, rtz.x, pc.x, ptz.x, two_r0) * igt : 0.0;
-                const double t1 = has_t ? bflux(rc.y, rtz.y, pc.y, ptz.y, two_r0) * igt : 0.0;
-                const double b0 = has_b ? bflux(rbz.x, rc.x, pbz.x, pc.x, two_r0) * igb : 0.0;
-                const double b1 = has_b ? bflux(rbz.y, rc.y, pbz.y, pc.y, two_r0) * igb : 0.0;
-                d0 += (t0 - b0) * ih;
-                d1 += (t1 - b1) * ih;
-                v0 = d0 + rho0 * fv.x;
-                v1 = d1 + rho0 * fv.y;
-            } else {  // residual r - mean - L p
-                const double2 rin = reinterpret_cast<const double2*>(a.r_in)[c2];
-                double l0 = ((pc.y - pc.x) - (pc.x - pw)) * idx2;
-                double l1 = ((pe - pc.y) - (pc.y - pc.x)) * idx2;
-                l0 += ((pn.x - pc.x) - (pc.x - ps.x)) * idy2;
-                l1 += ((pn.y - pc.y) - (pc.y - ps.y)) * idy2;
-                l0 += ((has_t ? (ptz.x - pc.x) * igt : 0.0) - (has_b ? (pc.x - pbz.x) * igb : 0.0)) * ih;
-                l1 += ((has_t ? (ptz.y - pc.y) * igt : 0.0) - (has_b ? (pc.y - pbz.y) * igb : 0.0)) * ih;
-                const double rp0 = rin.x - mean, rp1 = rin.y - mean;
-                v0 = rp0 - l0;
-                v1 = rp1 - l1;
-                res2 += v0 * v0 + v1 * v1;
-                r2 += rp0 * rp0 + rp1 * rp1;
+        return (((size_t)k * g.ny + j0 + line) * nx) / 2 + (t - line * M);  // double2 index
+    };
+    auto prefetch = [&](int t0, Pre* pre) {
+#pragma unroll
+        for (int u = 0; u < PF; ++u) {
+            const int t = t0 + u * 256;
+            pre[u].ptz = pre[u].pbz = double2{0.0, 0.0};
+            pre[u].rtz = pre[u].rbz = double2{1.0, 1.0};
+            if (t < npair) {
+                const size_t c2 = pair_index(t);
+                pre[u].f = fg[c2];
+                if (MODE != FWD_CONST) {
+                    if (has_t) pre[u].ptz = pg[c2 + plane / 2];
+                    if (has_b) pre[u].pbz = pg[c2 - plane / 2];
+                }
+                if (MODE == FWD_METHOD1) {
+                    if (has_t) pre[u].rtz = rg[c2 + plane / 2];
+                    if (has_b) pre[u].rbz = rg[c2 - plane / 2];
+                }
             }
         }
-        if (a.r_out) reinterpret_cast<double2*>(a.r_out)[c2] = double2{v0, v1};
-        rsum += v0 + v1;
-        buf0[line * M + n] = C{(TC)v0, (TC)v1};
+    };
+    Pre cur[PF];
+    prefetch(threadIdx.x, cur);
+    if (MODE != FWD_CONST) {
+        for (int t = threadIdx.x; t < (lb + 2) * M; t += 256) {
+            const int rr = t / M;
+            const int q = t - rr * M;
+            int j = j0 - 1 + rr;
+            j = (j < 0) ? j + g.ny : (j >= g.ny ? j - g.ny : j);
+            const size_t src = ((size_t)k * g.ny + j) * M + q;
+            pt[t] = pg[src];
+            if (MODE == FWD_METHOD1) rt[t] = rg[src];
+        }
+        __syncthreads();
+    }
+    for (int t0 = threadIdx.x; t0 < npair; t0 += PF * 256) {
+        if (t0 != (int)threadIdx.x) prefetch(t0, cur);
+#pragma unroll
+        for (int u = 0; u < PF; ++u) {
+            const int t = t0 + u * 256;
+            if (t >= npair) break;
+            const int line = t / M;
+            const int n = t - line * M;
+            const size_t c2 = pair_index(t);
+            const Pre& q = cur[u];
+            double v0, v1;
+            if (MODE == FWD_CONST) {
+                v0 = q.f.x * sc;
+                v1 = q.f.y * sc;
+            } else {
+                const double2* P = pt + (line + 1) * M;
+                const double2 pc = P[n], pn = P[n + M], ps = P[n - M];
+                const double pw = P[n == 0 ? M - 1 : n - 1].y, pe = P[n + 1 == M ? 0 : n + 1].x;
+                const double2 ptz = q.ptz, pbz = q.pbz;
+                if (MODE == FWD_METHOD1) {
+                    const double2* R = rt + (line + 1) * M;
+                    const double2 rc = R[n], rn = R[n + M], rs = R[n - M];
+                    const double rw = R[n == 0 ? M - 1 : n - 1].y, re = R[n + 1 == M ? 0 : n + 1].x;
+                    const double2 rtz = q.rtz, rbz = q.rbz;
+                    // x faces: west of 2n, between the pair, east of 2n+1
+                    const double fw = bflux(rw, rc.x, pw, pc.x, two_r0);
+                    const double fm = bflux(rc.x, rc.y, pc.x, pc.y, two_r0);
+                    const double fe = bflux(rc.y, re, pc.y, pe, two_r0);
+                    double d0 = (fm - fw) * idx2, d1 = (fe - fm) * idx2;
+                    d0 += (bflux(rc.x, rn.x, pc.x, pn.x, two_r0) - bflux(rs.x, rc.x, ps.x, pc.x, two_r0)) * idy2;
+                    d1 += (bflux(rc.y, rn.y, pc.y, pn.y, two_r0) - bflux(rs.y, rc.y, ps.y, pc.y, two_r0)) * idy2;
+                    const double t0z = has_t ? bflux(rc.x, rtz.x, pc.x, ptz.x, two_r0) * igt : 0.0;
+                    const double t1z = has_t ? bflux(rc.y, rtz.y, pc.y, ptz.y, two_r0) * igt : 0.0;
+                    const double b0z = has_b ? bflux(rbz.x, rc.x, pbz.x, pc.x, two_r0) * igb : 0.0;
+                    const double b1z = has_b ? bflux(rbz.y, rc.y, pbz.y, pc.y, two_r0) * igb : 0.0;
+                    d0 += (t0z - b0z) * ih;
+                    d1 += (t1z - b1z) * ih;
+                    v0 = d0 + rho0 * q.f.x;
+                    v1 = d1 + rho0 * q.f.y;
+                } else {  // residual r - mean - L p
+                    double l0 = ((pc.y - pc.x) - (pc.x - pw)) * idx2;
+                    double l1 = ((pe - pc.y) - (pc.y - pc.x)) * idx2;
+                    l0 += ((pn.x - pc.x) - (pc.x - ps.x)) * idy2;
+                    l1 += ((pn.y - pc.y) - (pc.y - ps.y)) * idy2;
+                    l0 += ((has_t ? (ptz.x - pc.x) * igt : 0.0) - (has_b ? (pc.x - pbz.x) * igb : 0.0)) * ih;
+                    l1 += ((has_t ? (ptz.y - pc.y) * igt : 0.0) - (has_b ? (pc.y - pbz.y) * igb : 0.0)) * ih;
+                    const double rp0 = q.f.x - mean, rp1 = q.f.y - mean;
+                    v0 = rp0 - l0;
+                    v1 = rp1 - l1;
+                    res2 += v0 * v0 + v1 * v1;
+                    r2 += rp0 * rp0 + rp1 * rp1;
+                }
+            }
+            if (a.r_out) reinterpret_cast<double2*>(a.r_out)[c2] = double2{v0, v1};
+            rsum += v0 + v1;
+            buf0[line * M + n] = C{(TC)v0, (TC)v1};
+        }
     }
     if (MODE != FWD_RESID && a.partials) {
         // FP64 volume-weighted sum of the right-hand side (its mean is the

@@ -76,6 +76,8 @@ void validate_opts(const psv_opts* o) {
     if (o->autotune < 0 || o->autotune > 2) fail(PSV_ERR_INVALID_ARG, "autotune must be 0..2");
     if (o->batch_executor < 0 || o->batch_executor > 2)
         fail(PSV_ERR_INVALID_ARG, "batch_executor must be 0..2");
+    if (o->chunk_rows != 0 && o->chunk_rows != 4 && o->chunk_rows != 8 && o->chunk_rows != 16)
+        fail(PSV_ERR_INVALID_ARG, "chunk_rows must be 0, 4, 8 or 16");
 }
 
 void default_opts(psv_opts* o) {
@@ -87,6 +89,7 @@ void default_opts(psv_opts* o) {
     o->check_inputs = 0;
     o->autotune = 0;
     o->batch_executor = 0;
+    o->chunk_rows = 0;
 }
 
 // exp(-2 pi i t / n), t = 0..n-1, from the angle reduced to the first octant
@@ -196,7 +199,9 @@ void plan_init(Plan& p, const psv_grid& g, const psv_opts& o, bool alloc_ws) {
     // takes at most 48 KiB of LDS (three blocks per CU), else the largest
     // that fits a block at all
     const size_t csz = p.opts.precision == PSV_MIXED ? sizeof(float2) : sizeof(double2);
-    int kc = 0;
+    int kc = p.opts.chunk_rows;
+    if (kc && !kc_fits(p, kc))
+        fail(PSV_ERR_UNSUPPORTED_SIZE, "the y tile of chunk_rows planes exceeds the LDS of a block");
     for (int c : {16, 8, 4})
         if (!kc && yz_lds(p.ny, c, csz) <= 48 * 1024) kc = c;
     if (!kc)

@@ -52,6 +52,24 @@ def test_small_uneven_batch(gpu, precision, tol, executor):
             assert infos[i].rho0_used == float(rho.min())
 
 
+@pytest.mark.parametrize("executor,kc", [("passes", 4), ("passes", 8), ("persistent", 4)])
+def test_small_uneven_batch_chunk_rows(gpu, executor, kc):
+    """Fixed chunk rows of the wall-normal partition in every problem of the
+    batch (ragged last chunks included), FP64 against the oracle."""
+    cases = _cases(SMALL, seed0=60)
+    ins = [oracle_inputs(c) for c in cases]
+    grids = [gpu.Grid.from_spec(c.grid) for c in cases]
+    say(f"executor {executor} chunk rows {kc}")
+    batch = gpu.Batch(grids, precision="fp64", executor=executor, chunk_rows=kc)
+    outs, infos = batch.solve([dev(x[1]) for x in ins], [dev(x[2]) for x in ins],
+                              [dev(x[3]) for x in ins], info=True)
+    for i, (g, f, rho, pp) in enumerate(ins):
+        (po,), _ = O.solve(f, g, rho, pp, with_relres=False)
+        e = rel_max_err(host(outs[i]), po)
+        assert e <= 1e-11, (i, e)
+        assert infos[i].relres <= 1e-12
+
+
 def test_batch_explicit_rho0_and_const(gpu):
     cases = _cases(SMALL[:3], seed0=40)
     ins = [oracle_inputs(c) for c in cases]

@@ -120,6 +120,51 @@ def test_mixed_refinement_small(gpu, shape):
     assert err <= 1e-8
 
 
+# Every chunk size of the wall-normal partition against the oracle: ragged
+# last chunks (nz not a multiple of kc), a single chunk shorter than kc,
+# three planes only, and runtime-length y FFTs (ny = 18, 6).
+KC_SHAPES = [
+    ((32, 48, 17), False),
+    ((12, 18, 10), True),
+    ((64, 32, 40), True),
+    ((16, 64, 3), False),
+    ((8, 6, 9), True),
+]
+
+
+@pytest.mark.parametrize("kc", [4, 8, 16])
+@pytest.mark.parametrize("shape,stretched", KC_SHAPES)
+def test_chunk_rows_fp64(gpu, kc, shape, stretched):
+    nx, ny, nz = shape
+    spec = W.GridSpec(nx, ny, nz, 1.0, 0.9, 1.1, W.tanh_faces(nz, 1.1, 1.5) if stretched else None)
+    case = W.two_phase_case("chunks", spec, 1, 11, n_spheres=3)
+    g, f, rho, pp = oracle_inputs(case)
+    say(f"chunk rows {kc} {shape} stretched={stretched}")
+    plan = gpu.Plan(gpu.Grid.from_spec(spec), chunk_rows=kc)
+    assert plan.launch_shape()[1] == kc
+    ps, _ = O.solve(f, g, rho, pp, n_steps=2)
+    p, info = plan.solve(dev(f), rho=dev(rho), p_prev=dev(pp), n_steps=2, info=True)
+    err = rel_max_err(host(p), ps[1])
+    say(f"  err {err:.3e} relres {info.relres:.3e}")
+    assert err <= TOL_FP64
+    assert info.relres <= 1e-12
+
+
+@pytest.mark.parametrize("kc", [4, 8, 16])
+def test_chunk_rows_mixed(gpu, kc):
+    spec = W.GridSpec(48, 32, 37, 1.0, 1.0, 1.5, W.tanh_faces(37, 1.5, 1.5))
+    case = W.two_phase_case("chunks_mixed", spec, 2, 12, n_spheres=6)
+    g, f, rho, pp = oracle_inputs(case)
+    say(f"mixed chunk rows {kc}")
+    plan = gpu.Plan(gpu.Grid.from_spec(spec), precision="mixed", chunk_rows=kc)
+    p, info = plan.solve(dev(f), rho=dev(rho), p_prev=dev(pp), info=True)
+    (po,), _ = O.solve(f, g, rho, pp)
+    err = rel_max_err(host(p), po)
+    say(f"  err {err:.3e} relres {info.relres:.3e} steps {info.refine_steps}")
+    assert info.relres <= 1e-10
+    assert err <= 1e-8
+
+
 def test_density_and_divergence_kernels(gpu):
     spec = W.GridSpec(24, 16, 10, 1.0, 1.0, 1.0, W.tanh_faces(10, 1.0, 1.5))
     case = W.two_phase_case("aux", spec, 1, 3, n_spheres=5)
