@@ -354,6 +354,14 @@ __device__ __forceinline__ void run_kind(int kind, const ProblemDesc& D, const P
     }
 }
 
+// Tickets hand out TICKET_TASKS consecutive tasks at a time. The queue is
+// ordered by pass, so a run of tasks usually shares its (problem, pass): the
+// block waits on that group's dependency once and releases its completions
+// with one counter update. The smallest unfinished task always has its
+// dependencies (earlier in the queue) done and is the current task of its
+// block, so the executor cannot deadlock.
+constexpr int TICKET_TASKS = 32;
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_batch_persistent(PersistArgs A) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -361,33 +369,47 @@ __global__ void __launch_bounds__(256) k_batch_persistent(PersistArgs A) {
     __shared__ int s_task;
     for (;;) {
         __syncthreads();  // the previous task is done with LDS and s_task
-        if (threadIdx.x == 0) s_task = atomicAdd(A.ticket, 1);
+        if (threadIdx.x == 0) s_task = atomicAdd(A.ticket, TICKET_TASKS);
         __syncthreads();
-        const int t = s_task;
-        if (t >= A.ntasks) break;
-        const int4 tk = A.tasks[t];
-        int* cnt = A.counters + (size_t)tk.x * A.nlevels;
-        if (threadIdx.x == 0 && tk.y > 0) {
-            long long spins = 0;
-            while (__hip_atomic_load(cnt + tk.y - 1, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < tk.w) {
-                __builtin_amdgcn_s_sleep(2);
-                if (++spins > SPIN_LIMIT) {
-                    atomicOr(A.error, 1);
-                    break;
+        const int t0 = s_task;
+        if (t0 >= A.ntasks) break;
+        const int t1 = min(t0 + TICKET_TASKS, A.ntasks);
+        int* cnt_done = nullptr;  // counter of the group whose completions are pending
+        int pending = 0;
+        for (int t = t0; t < t1; ++t) {
+            const int4 tk = A.tasks[t];
+            int* cnt = A.counters + (size_t)tk.x * A.nlevels;
+            if (cnt + tk.y != cnt_done) {
+                if (pending && threadIdx.x == 0) {
+                    __threadfence();
+                    __hip_atomic_fetch_add(cnt_done, pending, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
                 }
-                // once any wait has failed, no block waits again: the drain is bounded
-                if ((spins & 255) == 0 &&
-                    __hip_atomic_load(A.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-                    break;
+                pending = 0;
+                cnt_done = cnt + tk.y;
+                if (threadIdx.x == 0 && tk.y > 0) {
+                    long long spins = 0;
+                    while (__hip_atomic_load(cnt + tk.y - 1, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < tk.w) {
+                        __builtin_amdgcn_s_sleep(2);
+                        if (++spins > SPIN_LIMIT) {
+                            atomicOr(A.error, 1);
+                            break;
+                        }
+                        // once any wait has failed, no block waits again: the drain is bounded
+                        if ((spins & 255) == 0 &&
+                            __hip_atomic_load(A.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+                            break;
+                    }
+                }
+                __syncthreads();
+                __threadfence();  // every wave observes the producers' writes
             }
+            run_kind<T>(A.kinds[tk.y], A.desc[tk.x], A.io[tk.x], tk.z, smem_raw, red);
+            __syncthreads();  // the tile is complete and its LDS free
+            ++pending;
         }
-        __syncthreads();
-        __threadfence();  // every wave observes the producers' writes
-        run_kind<T>(A.kinds[tk.y], A.desc[tk.x], A.io[tk.x], tk.z, smem_raw, red);
-        __syncthreads();
         if (threadIdx.x == 0) {
             __threadfence();
-            __hip_atomic_fetch_add(cnt + tk.y, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(cnt_done, pending, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
 }

@@ -378,7 +378,7 @@ template <typename T>
 __device__ __forceinline__ void ifc_tile(const ZArgs& z, c2<T>* __restrict__ spec, int b,
                                          unsigned char* smem) {
     using C = c2<T>;
-    constexpr int SEG = sizeof(T) == 8 ? 16 : 32;
+    constexpr int SEG = 16;
     const int S = z.mx * z.ny;
     const size_t SP = (size_t)S;
     if (b == 0) {
