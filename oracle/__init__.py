@@ -14,7 +14,10 @@ liquid-gas flows at low-Mach number" (arXiv:2005.11806):
 * one step solved exactly by eigenexpansion (Sec. 3.3.1): forward DFTs in
   the two periodic directions, one tridiagonal solve per wavenumber pair in
   the wall-normal direction, inverse DFTs;
-* the adjoint of one step (gradients of sum(w p)).
+* the adjoint of one step (gradients of sum(w p));
+* Method III (Sec. 3.3.1, Eq. new_poisson) and its loop (Algorithm 1): the
+  recast through the correction step, iterated with the velocity until the
+  summed divergence residual reaches its threshold (``oracle.method3``).
 
 Every routine is the plain definition: matrix-form DFTs, a textbook Thomas
 sweep, explicit stencils. Parity-pinned by ``tests/test_oracle_*.py``
@@ -29,10 +32,11 @@ from .tridiag import thomas, z_coefficients, eigen_x, eigen_y
 from .solve import solve_const, method1_step, solve, relres, SolveInfo
 from .adjoint import adjoint_step
 from . import dense
+from . import method3
 
 __all__ = [
     "Grid", "face_density", "grad", "div", "laplacian", "assemble_method1", "mixture_density",
     "divergence_of_faces", "rdft_x", "dft_y", "idft_y", "irdft_x", "thomas", "z_coefficients",
     "eigen_x", "eigen_y", "solve_const", "method1_step", "solve", "relres", "SolveInfo",
-    "adjoint_step", "dense",
+    "adjoint_step", "dense", "method3",
 ]
