@@ -73,6 +73,8 @@ def kernel_bytes(name, nx, ny, nz, kc=None):
         return 2 * 8 * n + c * ns
     if name.startswith("fwd_x_const"):
         return 8 * n + c * ns
+    if name.startswith("fwd_x_method3"):
+        return 3 * 8 * n + c * ns
     if name.startswith("yz_"):
         return 2 * c * ns
     if name.startswith("z_interface"):
@@ -134,7 +136,7 @@ def trace_name(rocprof_name):
     prec = "fp32" if "<float" in n else "fp64"
     if "k_fwd_x<" in n:
         mode = n.split("k_fwd_x<")[1].split(",")[2].strip()
-        return f"fwd_x_{['const', 'method1', 'resid'][int(mode)]}_{prec}"
+        return f"fwd_x_{['const', 'method1', 'resid', 'method3'][int(mode)]}_{prec}"
     if "k_inv_x<" in n:
         mode = n.split("k_inv_x<")[1].split(",")[2].strip()
         return f"inv_x_{['store', 'add', 'scale'][int(mode)]}_{prec}"
@@ -238,6 +240,77 @@ BATCH_WORKLOADS = {
 }
 
 
+METHOD3_WORKLOADS = {
+    "method3_128": ("fp64", "128^3 uniform, Method III with its loop (Algorithm 1), 20 spheres, "
+                    "rho_l=10, rho_g=1-5, target divergence in the gas, dt=1e-3, to "
+                    "eps <= 1e-10 eps(u*); FP64 solves"),
+    "method3_128_mixed": ("mixed", "same Method III problem and threshold; FP32 solves inside the "
+                          "loop (the loop corrects them)"),
+}
+
+
+def bench_method3(args):
+    """Pressure solves per second of Method III's whole loop (grid points /
+    time per Algorithm-1 call), iterations and the dominant kernel."""
+    import torch
+    import paper_2005_11806_amd as psv
+    import workloads as W
+    prec, desc = METHOD3_WORKLOADS[args.workload]
+    case = W.method3_128()
+    spec = case.base.grid
+    dev = torch.device("cuda:0")
+    to = lambda a: torch.from_numpy(a).to(dev)  # noqa: E731
+    plan = psv.Plan(psv.Grid.from_spec(spec), precision=prec, autotune=args.autotune)
+    U = tuple(to(u) for u in case.base.faces)
+    T = to(case.div_target)
+    R = plan.density_from_colour(to(case.base.phi), to(case.base.rho_gas), case.base.rho_liq)
+    p = torch.empty(spec.nz, spec.ny, spec.nx, dtype=torch.float64, device=dev)
+    _, _, info = plan.solve_method3(U, T, R, case.dt, eps_t=0.0, max_iter=1, out=p)
+    eps_t = 1e-10 * info.eps_start
+
+    def step():
+        return plan.solve_method3(U, T, R, case.dt, eps_t=eps_t, max_iter=500, out=p, u_out=True)
+
+    _, _, info = step()
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ms = 1e3 * el / args.steps
+    plan.trace(True)
+    step()
+    torch.cuda.synchronize()
+    summary = plan.trace_summary()
+    plan.trace(False)
+    dom = max(summary, key=lambda k: summary[k][1])
+    launches, total_ms = summary[dom]
+    avg_s = total_ms / launches * 1e-3
+    kc = plan.launch_shape()[1]
+    alg = kernel_bytes(dom, spec.nx, spec.ny, spec.nz, kc)
+    ach = alg / avg_s / 1e9 if alg else None
+    line = {
+        "metric": METRIC, "value": spec.n * args.steps / el, "unit": "grid_pts/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64" if prec == "fp64" else "f32+f64",
+        "data": "synthetic (seeded generators in workloads/)",
+        "config": {"workload": f"{args.workload}: {desc}", "grid": [spec.nx, spec.ny, spec.nz],
+                   "iterations": info.iterations, "converged": info.converged,
+                   "eps": info.eps, "eps_start": info.eps_start,
+                   "ms_per_iteration": ms / max(info.iterations, 1)},
+        "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": ach / HBM_PEAK_GBS if ach else None, "traffic": None, "kernel": dom,
+                     "avg_launch_us": avg_s * 1e6, "algorithmic_bytes": alg, "chunk_rows": kc,
+                     "kernels": {k: kernel_row(k, v, spec, kc) for k, v in
+                                 sorted(summary.items(), key=lambda kv: -kv[1][1])}},
+        "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def bench_batch(args):
     """Throughput of the 64-problem uneven batch (total grid points per second)."""
     import torch
@@ -308,7 +381,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="vd128", choices=sorted(WORKLOADS) + sorted(BATCH_WORKLOADS))
+    ap.add_argument("--workload", default="vd128",
+                    choices=sorted(WORKLOADS) + sorted(BATCH_WORKLOADS) + sorted(METHOD3_WORKLOADS))
     ap.add_argument("--mode", default="graph", choices=["graph", "eager"])
     ap.add_argument("--autotune", type=int, default=1, choices=[0, 1],
                     help="tune launch shapes at plan creation (outside the timed region)")
@@ -332,6 +406,9 @@ def main():
 
     if args.workload in BATCH_WORKLOADS:
         bench_batch(args)
+        return
+    if args.workload in METHOD3_WORKLOADS:
+        bench_method3(args)
         return
 
     if args.copy_probe:

@@ -141,6 +141,45 @@ psv_status psv_solve_adjoint(psv_plan* plan, const double* w, const double* f, c
                              double rho0, const double* p_prev, double* grad_f, double* grad_rho,
                              double* grad_p_prev, double* grad_rho0_host, void* stream);
 
+/* Method III (Sec. 3.3.1, Eq. new_poisson) solved with its loop (Algorithm 1):
+ *     lap p^{s+1} = (1/dt) [ D(rho u*) - rho div_target - u^s . grad rho ],
+ *     u^{s+1}     = u* - dt rho_f^-1 G p^{s+1}          (Eq. corr),
+ * from u^0 = u* (or from the pressure p_init), until
+ *     eps = sum over cells of |div u^{s+1} - div_target| <= eps_t
+ * or max_iter solves. rho_f is the arithmetic mean of the two cells of a face
+ * and u . grad rho the discrete product-rule remainder D(rho_f u) - rho D u,
+ * which makes the recast exact on the grid: a converged u meets div_target
+ * in every cell, and p solves div(rho^-1 grad p) = (div u* - div_target)/dt.
+ * Each iteration is the eigenexpansion solve of the plan (FP64, or FP32 for a
+ * MIXED plan: the loop itself corrects the FP32 solves). Uses the plan's
+ * workspace; synchronises once per iteration to read eps.
+ *   ux, uy     [nz][ny][nx]   u* on the x face between cells i and i+1 (and
+ *                             the y face between j and j+1), periodic
+ *   uz         [nz+1][ny][nx] u* on the z face below cell k; the planes 0 and
+ *                             nz are the walls (normal velocity 0)
+ *   div_target [nz][ny][nx]   div u^{n+1}; its volume-weighted mean must be 0
+ *                             (a closed domain cannot meet the mean part)
+ *   rho        [nz][ny][nx]   density > 0;  dt > 0
+ *   eps_t >= 0 absolute threshold on eps; max_iter in [1, 100000]
+ *   p_init     optional starting pressure (may equal p_out); NULL starts
+ *              from u* (p = 0)
+ *   p_out      pressure (zero volume-weighted mean)
+ *   ux_out, uy_out, uz_out  the corrected velocity u^{n+1}, same layouts as
+ *              u*: all three or none (NULL); must not alias u*
+ * Stops without error when max_iter is reached (info->converged = 0). */
+typedef struct {
+    int32_t iterations;      /* eigenexpansion solves performed */
+    int32_t converged;       /* 1 when eps <= eps_t */
+    double eps;              /* eps of the returned p and u */
+    double eps_start;        /* eps of u* itself (NaN when p_init is given) */
+} psv_m3_info;
+
+psv_status psv_solve_method3(psv_plan* plan, const double* ux, const double* uy, const double* uz,
+                             const double* div_target, const double* rho, double dt, double eps_t,
+                             int32_t max_iter, const double* p_init, double* p_out,
+                             double* ux_out, double* uy_out, double* uz_out, void* stream,
+                             psv_m3_info* info);
+
 /* Mixture density of Sec. 2.2, Eq. eq_22, with the colour Phi = 1 in gas:
  * rho = rho_gas * Phi + rho_liq * (1 - Phi). phi and rho_gas are device fields. */
 psv_status psv_density_from_colour(const psv_plan* plan, const double* phi, const double* rho_gas,

@@ -72,6 +72,14 @@ class SolveInfo:
     rho0_used: float
 
 
+@dataclasses.dataclass
+class Method3Info:
+    iterations: int      # eigenexpansion solves performed
+    converged: bool      # eps <= eps_t
+    eps: float           # sum over cells of |div u - div_target| of the result
+    eps_start: float     # the same for u* (nan when started from p_init)
+
+
 _PREC = {"fp64": _abi.PSV_FP64, "mixed": _abi.PSV_MIXED}
 _METH = {"const": _abi.PSV_CONST, "method1": _abi.PSV_SPLIT_RHO0}
 
@@ -189,6 +197,31 @@ class Plan:
         if grad_rho0:
             out["rho0"] = r0.value
         return out
+
+    def solve_method3(self, u_star, div_target, rho, dt, eps_t=0.0, max_iter=50, p_init=None,
+                      out=None, u_out=False, stream=None):
+        """Method III with its loop (psv_solve_method3). u_star = (ux, uy, uz)
+        face tensors ([nz][ny][nx] twice, [nz+1][ny][nx]). Returns
+        (p, (ux, uy, uz) or None, Method3Info)."""
+        import torch
+        sh = self.shape
+        nz, ny, nx = sh
+        ux, uy, uz = u_star
+        if out is None:
+            out = torch.empty(sh, dtype=torch.float64, device=rho.device)
+        uo = None
+        if u_out:
+            uo = (torch.empty(sh, dtype=torch.float64, device=rho.device),
+                  torch.empty(sh, dtype=torch.float64, device=rho.device),
+                  torch.empty((nz + 1, ny, nx), dtype=torch.float64, device=rho.device))
+        inf = _abi.psv_m3_info()
+        check(lib().psv_solve_method3(
+            self._h, _ptr(ux, sh, "ux"), _ptr(uy, sh, "uy"), _ptr(uz, (nz + 1, ny, nx), "uz"),
+            _ptr(div_target, sh, "div_target"), _ptr(rho, sh, "rho"), float(dt), float(eps_t),
+            int(max_iter), _ptr(p_init, sh, "p_init"), _ptr(out, sh, "out"),
+            _ptr(uo[0], sh) if uo else None, _ptr(uo[1], sh) if uo else None,
+            _ptr(uo[2], (nz + 1, ny, nx)) if uo else None, _stream(stream), C.byref(inf)))
+        return out, uo, Method3Info(inf.iterations, bool(inf.converged), inf.eps, inf.eps_start)
 
     def density_from_colour(self, phi, rho_gas, rho_liq, out=None, stream=None):
         import torch

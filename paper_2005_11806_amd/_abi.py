@@ -36,6 +36,11 @@ class psv_info(C.Structure):
                 ("rhs_mean_removed", C.c_double), ("rho0_used", C.c_double)]
 
 
+class psv_m3_info(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("converged", C.c_int32), ("eps", C.c_double),
+                ("eps_start", C.c_double)]
+
+
 EXPORTS = {
     # name: (restype, argtypes)
     "psv_opts_default": (None, [C.POINTER(psv_opts)]),
@@ -48,6 +53,10 @@ EXPORTS = {
                             C.c_int32, C.c_void_p, C.POINTER(psv_info)]),
     "psv_solve_adjoint": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double,
                                     C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, dptr, C.c_void_p]),
+    "psv_solve_method3": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                    C.c_void_p, C.c_double, C.c_double, C.c_int32, C.c_void_p,
+                                    C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                    C.POINTER(psv_m3_info)]),
     "psv_density_from_colour": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_void_p,
                                           C.c_void_p]),
     "psv_divergence": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),

@@ -320,6 +320,84 @@ psv_status psv_solve_adjoint(psv_plan* plan, const double* w, const double* f, c
     });
 }
 
+psv_status psv_solve_method3(psv_plan* plan, const double* ux, const double* uy, const double* uz,
+                             const double* div_target, const double* rho, double dt, double eps_t,
+                             int32_t max_iter, const double* p_init, double* p_out,
+                             double* ux_out, double* uy_out, double* uz_out, void* stream,
+                             psv_m3_info* info) {
+    return guarded([&] {
+        need(plan != nullptr, "plan is NULL");
+        need(ux && uy && uz, "u* face arrays must be non-NULL");
+        need(div_target != nullptr, "div_target is NULL");
+        need(rho != nullptr, "rho is NULL");
+        need(p_out != nullptr, "p_out is NULL");
+        need(std::isfinite(dt) && dt > 0.0, "dt must be positive and finite");
+        need(std::isfinite(eps_t) && eps_t >= 0.0, "eps_t must be >= 0 and finite");
+        need(max_iter >= 1 && max_iter <= 100000, "max_iter must be in [1, 100000]");
+        const bool want_u = ux_out && uy_out && uz_out;
+        need(want_u || (!ux_out && !uy_out && !uz_out), "give all three velocity outputs or none");
+        if (want_u)
+            need(ux_out != ux && uy_out != uy && uz_out != uz, "velocity outputs must not alias u*");
+        Plan& P = plan->p;
+        const bool fp32 = P.opts.precision == PSV_MIXED;
+        hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+        PSV_HIP(hipSetDevice(P.device));
+        if (P.opts.check_inputs) {
+            check_field(P, rho, true, "rho", s);
+            check_field(P, div_target, false, "div_target", s);
+            check_field(P, ux, false, "ux", s);
+            check_field(P, uy, false, "uy", s);
+        }
+        const size_t n = P.ncell();
+        // f = (D u* - div_target) / dt, the loop-invariant part (Algorithm 1)
+        double* f = P.r_ws;
+        psv::launch_divergence_rhs(P, ux, uy, uz, div_target, 1.0 / dt, f, s);
+        bool has_p = p_init != nullptr;
+        if (has_p && p_init != p_out)
+            PSV_HIP(hipMemcpyAsync(p_out, p_init, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+        const int nb = psv::fwd_x_blocks(P);
+        double* qpart = P.partials + nb;  // sum |f - D(rho_f^-1 G p)| per block
+        const double inv_scale = 2.0 / ((double)P.nx * P.ny);
+        int iters = 0;
+        bool converged = false;
+        double eps = NAN;
+        for (;;) {
+            psv::FwdArgs a{};
+            a.mode = psv::FWD_METHOD3;
+            a.f = f;
+            a.rho = rho;
+            a.pprev = has_p ? p_out : nullptr;
+            a.partials_abs = qpart;
+            psv::launch_fwd_x(P, fp32, a, s);
+            psv::launch_sum_partials(P, qpart, nb, P.scal + (has_p ? psv::S_EPS : psv::S_EPS0), s);
+            if (has_p) {
+                // the residual of the current iterate decides before solving again
+                sync_read(P, s);
+                eps = dt * P.host_scal[psv::S_EPS];
+                if (!std::isfinite(eps)) psv::fail(PSV_ERR_NONFINITE, "Method III residual is not finite");
+                if (eps <= eps_t) {
+                    converged = true;
+                    break;
+                }
+                if (iters >= max_iter) break;
+            }
+            psv::launch_z_solve(P, fp32, P.scal + psv::S_MEAN2, nullptr, s);
+            psv::launch_inv_x(P, fp32, has_p ? psv::INV_ADD : psv::INV_STORE, p_out, inv_scale,
+                              nullptr, s);
+            has_p = true;
+            ++iters;
+        }
+        if (want_u) psv::launch_correct_velocity(P, ux, uy, uz, p_out, rho, dt, ux_out, uy_out, uz_out, s);
+        if (info) {
+            sync_read(P, s);
+            info->iterations = iters;
+            info->converged = converged ? 1 : 0;
+            info->eps = eps;
+            info->eps_start = p_init ? NAN : dt * P.host_scal[psv::S_EPS0];
+        }
+    });
+}
+
 psv_status psv_density_from_colour(const psv_plan* plan, const double* phi, const double* rho_gas,
                                    double rho_liq, double* rho_out, void* stream) {
     return guarded([&] {

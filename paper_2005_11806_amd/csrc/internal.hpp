@@ -41,7 +41,9 @@ Radices make_radices(int n);
 enum FwdMode : int {
     FWD_CONST = 0,    // r = f * scale[k] (scale may be null)
     FWD_METHOD1 = 1,  // r = rho0 f + D((1 - rho0/rho_f) G p_prev)
-    FWD_RESID = 2     // r = r_in - mean - L p (refinement residual), norm partials
+    FWD_RESID = 2,    // r = r_in - mean - L p (refinement residual), norm partials
+    FWD_METHOD3 = 3   // r = rho (f - D(rho_f^-1 G p)) (Method III correction; p may be
+                      // null, read as 0), partials of sum |f - D(rho_f^-1 G p)|
 };
 // Store modes of the inverse x pass.
 enum InvMode : int {
@@ -59,6 +61,8 @@ enum Scalar : int {
     S_RELRES = 4,
     S_GRAD_RHO0 = 5,
     S_MEAN2 = 6,       // mean removed by a refinement solve (discarded)
+    S_EPS = 7,         // Method III: sum |f - D(rho_f^-1 G p)| of the current iterate
+    S_EPS0 = 8,        // Method III: the same for p = 0 (u = u*)
     S_NSCAL = 16
 };
 enum Flag : int { F_DONE = 0, F_ARGMIN = 1, F_STEPS = 2, F_NFLAG = 8 };
@@ -166,6 +170,7 @@ struct FwdArgs {
     const double* rho0;   // device scalar
     const double* mean;   // RESID: device scalar (mean removed from r)
     double* partials;     // RESID: 2 per block
+    double* partials_abs; // METHOD3: sum |f - D(rho_f^-1 G p)| per block
     const int* done;      // skip when *done != 0 (may be null)
 };
 void launch_fwd_x(const Plan& p, bool fp32, const FwdArgs& a, hipStream_t s);
@@ -193,6 +198,16 @@ void launch_density(const Plan& p, const double* phi, const double* rg, double r
                     hipStream_t s);
 void launch_divergence(const Plan& p, const double* ux, const double* uy, const double* uz,
                        double* out, hipStream_t s);
+// out = scale (D u - target); target may be null
+void launch_divergence_rhs(const Plan& p, const double* ux, const double* uy, const double* uz,
+                           const double* target, double scale, double* out, hipStream_t s);
+// Method III correction u = u* - dt rho_f^-1 G p on the faces
+void launch_correct_velocity(const Plan& p, const double* ux, const double* uy, const double* uz,
+                             const double* pr, const double* rho, double dt, double* ox,
+                             double* oy, double* oz, hipStream_t s);
+// out = sum of partials[0 .. nblocks)
+void launch_sum_partials(const Plan& p, const double* partials, int nblocks, double* out,
+                         hipStream_t s);
 void launch_adjoint_faces(const Plan& p, const double* x, const double* f, const double* rho,
                           const double* pprev, const double* rho0, double* grad_f,
                           double* grad_rho, double* grad_p, double* partials, hipStream_t s);

@@ -197,20 +197,58 @@ __global__ void k_density(size_t n, const double* __restrict__ phi, const double
     }
 }
 
+// (i, j, k) of cell c with 32-bit arithmetic (every index is below 2^31)
+__device__ __forceinline__ void cell_ijk(unsigned c, const Geo& g, unsigned& i, unsigned& j,
+                                         unsigned& k) {
+    const unsigned line = c / (unsigned)g.nx;
+    i = c - line * (unsigned)g.nx;
+    k = line / (unsigned)g.ny;
+    j = line - k * (unsigned)g.ny;
+}
+
+// out = scale (D u - target), target may be null. u is the MAC face field:
+// ux on the face between cells i and i+1, uy likewise, uz [nz+1][ny][nx] with
+// the bottom face of cell c at index c and the top at c + nx ny.
 __global__ void k_divergence(Geo g, const double* __restrict__ ux, const double* __restrict__ uy,
-                             const double* __restrict__ uz, double* __restrict__ out) {
-    const size_t n = (size_t)g.nx * g.ny * g.nz;
-    const size_t plane = (size_t)g.nx * g.ny;
-    for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < n;
-         c += (size_t)gridDim.x * blockDim.x) {
-        int i, j, k;
-        cell_coords(c, g, i, j, k);
-        const size_t row = c - i;
-        const double dx = ux[c] - ux[row + (i == 0 ? g.nx - 1 : i - 1)];
-        const double dy = uy[c] - uy[c - (size_t)j * g.nx + (size_t)(j == 0 ? g.ny - 1 : j - 1) * g.nx];
-        // uz is [nz+1][ny][nx]: the bottom face of cell c has index c, the top c + plane
+                             const double* __restrict__ uz, const double* __restrict__ target,
+                             double scale, double* __restrict__ out) {
+    const unsigned nx = (unsigned)g.nx, plane = nx * (unsigned)g.ny;
+    const unsigned n = plane * (unsigned)g.nz;
+    for (unsigned c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) {
+        unsigned i, j, k;
+        cell_ijk(c, g, i, j, k);
+        const double dx = ux[c] - ux[i == 0 ? c + nx - 1 : c - 1];
+        const double dy = uy[c] - uy[j == 0 ? c + plane - nx : c - nx];
         const double dz = uz[c + plane] - uz[c];
-        out[c] = dx * g.inv_dx + dy * g.inv_dy + dz * g.inv_h[k];
+        double d = dx * g.inv_dx + dy * g.inv_dy + dz * g.inv_h[k];
+        if (target) d -= target[c];
+        out[c] = d * scale;
+    }
+}
+
+// Correction step of Method III (Eq. corr): u = u* - dt rho_f^-1 G p on every
+// interior face, rho_f = (rho_L + rho_R)/2; the two wall planes of uz are
+// copied (zero normal velocity).
+__global__ void k_correct_velocity(Geo g, const double* __restrict__ ux, const double* __restrict__ uy,
+                                   const double* __restrict__ uz, const double* __restrict__ p,
+                                   const double* __restrict__ rho, double dt,
+                                   double* __restrict__ ox, double* __restrict__ oy,
+                                   double* __restrict__ oz) {
+    const unsigned nx = (unsigned)g.nx, plane = nx * (unsigned)g.ny;
+    const unsigned n = plane * (unsigned)g.nz;
+    for (unsigned c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) {
+        unsigned i, j, k;
+        cell_ijk(c, g, i, j, k);
+        const double pc = p[c], rc = rho[c];
+        const unsigned ce = i + 1 == nx ? c + 1 - nx : c + 1;
+        const unsigned cn = j + 1 == (unsigned)g.ny ? c + nx - plane : c + nx;
+        ox[c] = ux[c] - dt * 2.0 * (p[ce] - pc) * g.inv_dx / (rc + rho[ce]);
+        oy[c] = uy[c] - dt * 2.0 * (p[cn] - pc) * g.inv_dy / (rc + rho[cn]);
+        if (k == 0)
+            oz[c] = uz[c];
+        else
+            oz[c] = uz[c] - dt * 2.0 * (pc - p[c - plane]) * g.inv_g[k] / (rho[c - plane] + rc);
+        if (k + 1 == (unsigned)g.nz) oz[c + plane] = uz[c + plane];
     }
 }
 
@@ -399,8 +437,30 @@ void launch_density(const Plan& p, const double* phi, const double* rg, double r
 
 void launch_divergence(const Plan& p, const double* ux, const double* uy, const double* uz,
                        double* out, hipStream_t s) {
+    launch_divergence_rhs(p, ux, uy, uz, nullptr, 1.0, out, s);
+}
+
+void launch_divergence_rhs(const Plan& p, const double* ux, const double* uy, const double* uz,
+                           const double* target, double scale, double* out, hipStream_t s) {
     const int nb = grid_blocks(p.ncell(), RB) * 4;
-    hipLaunchKernelGGL(k_divergence, dim3(nb), dim3(RB), 0, s, make_geo(p), ux, uy, uz, out);
+    hipLaunchKernelGGL(k_divergence, dim3(nb), dim3(RB), 0, s, make_geo(p), ux, uy, uz, target,
+                       scale, out);
+    PSV_HIP(hipGetLastError());
+}
+
+void launch_correct_velocity(const Plan& p, const double* ux, const double* uy, const double* uz,
+                             const double* pr, const double* rho, double dt, double* ox,
+                             double* oy, double* oz, hipStream_t s) {
+    const int nb = grid_blocks(p.ncell(), RB) * 4;
+    TraceScope ts(p, "correct_velocity", s);
+    hipLaunchKernelGGL(k_correct_velocity, dim3(nb), dim3(RB), 0, s, make_geo(p), ux, uy, uz, pr,
+                       rho, dt, ox, oy, oz);
+    PSV_HIP(hipGetLastError());
+}
+
+void launch_sum_partials(const Plan& p, const double* partials, int nblocks, double* out,
+                         hipStream_t s) {
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(RB), 0, s, partials, nblocks, 1, out);
     PSV_HIP(hipGetLastError());
 }
 

@@ -45,8 +45,9 @@ void fwd_impl(const Plan& p, const FwdArgs& a, hipStream_t s) {
     Stencil st{p.t.inv_h, p.t.inv_g, p.t.vol};
     const c2<TC>* tw;
     if constexpr (sizeof(TC) == 8) tw = p.t.twx64; else tw = p.t.twx32;
-    static const char* names[2][3] = {{"fwd_x_const_fp64", "fwd_x_method1_fp64", "fwd_x_resid_fp64"},
-                                      {"fwd_x_const_fp32", "fwd_x_method1_fp32", "fwd_x_resid_fp32"}};
+    static const char* names[2][4] = {
+        {"fwd_x_const_fp64", "fwd_x_method1_fp64", "fwd_x_resid_fp64", "fwd_x_method3_fp64"},
+        {"fwd_x_const_fp32", "fwd_x_method1_fp32", "fwd_x_resid_fp32", "fwd_x_method3_fp32"}};
     TraceScope ts(p, names[sizeof(TC) == 4][MODE], s);
     switch (g.M) {
 #define PSV_CASE(n) case n: fwd_launch<TC, TS, MODE, n>(p, g, st, a, tw, s); break;
@@ -91,12 +92,14 @@ void launch_fwd_x(const Plan& p, bool fp32, const FwdArgs& a, hipStream_t s) {
         switch (a.mode) {
             case FWD_CONST: fwd_impl<float, float, FWD_CONST>(p, a, s); break;
             case FWD_METHOD1: fwd_impl<float, float, FWD_METHOD1>(p, a, s); break;
+            case FWD_METHOD3: fwd_impl<float, float, FWD_METHOD3>(p, a, s); break;
             default: fwd_impl<float, float, FWD_RESID>(p, a, s); break;
         }
     } else {
         switch (a.mode) {
             case FWD_CONST: fwd_impl<double, double, FWD_CONST>(p, a, s); break;
             case FWD_METHOD1: fwd_impl<double, double, FWD_METHOD1>(p, a, s); break;
+            case FWD_METHOD3: fwd_impl<double, double, FWD_METHOD3>(p, a, s); break;
             default: fwd_impl<double, double, FWD_RESID>(p, a, s); break;
         }
     }

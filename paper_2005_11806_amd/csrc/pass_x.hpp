@@ -53,6 +53,12 @@ __device__ __forceinline__ double bflux(double rl, double rr, double pl, double 
     return (s - two_r0) * rcp_nr(s) * (pr - pl);
 }
 
+// rho_f^-1 (p_R - p_L) across the face between cells L and R,
+// rho_f = (rho_L + rho_R)/2.
+__device__ __forceinline__ double gflux(double rl, double rr, double pl, double pr) {
+    return 2.0 * rcp_nr(rl + rr) * (pr - pl);
+}
+
 // Blocks are dispatched round-robin over the 8 XCDs; remap so that each XCD
 // walks a contiguous range of (plane, tile) indices and the neighbouring
 // lines/planes read by the stencil stay in its L2.
@@ -114,7 +120,9 @@ __device__ __forceinline__ void fwd_x_tile(const XGeom& g, const Stencil& st, co
     const bool has_t = k + 1 < g.nz, has_b = k > 0;
     const double igt = has_t ? st.inv_g[k + 1] : 0.0, igb = has_b ? st.inv_g[k] : 0.0;
     const double ih = st.inv_h[k];
-    double res2 = 0.0, r2 = 0.0, rsum = 0.0;
+    double res2 = 0.0, r2 = 0.0, rsum = 0.0, qabs = 0.0;
+    // Method III without a pressure iterate reads p as 0
+    const bool has_p = MODE != FWD_METHOD3 || a.pprev != nullptr;
     // One thread per pair of cells (2n, 2n+1): exactly the packed input
     // z_n = r_{2n} + i r_{2n+1} of the half-length transform. The global
     // operands of a thread's next PF pairs (f or r_in, and p, rho on the
@@ -141,11 +149,11 @@ __device__ __forceinline__ void fwd_x_tile(const XGeom& g, const Stencil& st, co
             if (t < npair) {
                 const size_t c2 = pair_index(t);
                 pre[u].f = fg[c2];
-                if (MODE != FWD_CONST) {
+                if (MODE != FWD_CONST && has_p) {
                     if (has_t) pre[u].ptz = pg[c2 + plane / 2];
                     if (has_b) pre[u].pbz = pg[c2 - plane / 2];
                 }
-                if (MODE == FWD_METHOD1) {
+                if (MODE == FWD_METHOD1 || MODE == FWD_METHOD3) {
                     if (has_t) pre[u].rtz = rg[c2 + plane / 2];
                     if (has_b) pre[u].rbz = rg[c2 - plane / 2];
                 }
@@ -161,8 +169,8 @@ __device__ __forceinline__ void fwd_x_tile(const XGeom& g, const Stencil& st, co
             int j = j0 - 1 + rr;
             j = (j < 0) ? j + g.ny : (j >= g.ny ? j - g.ny : j);
             const size_t src = ((size_t)k * g.ny + j) * M + q;
-            pt[t] = pg[src];
-            if (MODE == FWD_METHOD1) rt[t] = rg[src];
+            pt[t] = has_p ? pg[src] : double2{0.0, 0.0};
+            if (MODE == FWD_METHOD1 || MODE == FWD_METHOD3) rt[t] = rg[src];
         }
         __syncthreads();
     }
@@ -205,6 +213,29 @@ __device__ __forceinline__ void fwd_x_tile(const XGeom& g, const Stencil& st, co
                     d1 += (t1z - b1z) * ih;
                     v0 = d0 + rho0 * q.f.x;
                     v1 = d1 + rho0 * q.f.y;
+                } else if (MODE == FWD_METHOD3) {
+                    // q = f - D(rho_f^-1 G p), r = rho q (cell density, Eq. new_poisson in
+                    // pressure form)
+                    const double2* R = rt + (line + 1) * M;
+                    const double2 rc = R[n], rn = R[n + M], rs = R[n - M];
+                    const double rw = R[n == 0 ? M - 1 : n - 1].y, re = R[n + 1 == M ? 0 : n + 1].x;
+                    const double2 rtz = q.rtz, rbz = q.rbz;
+                    const double fw = gflux(rw, rc.x, pw, pc.x);
+                    const double fm = gflux(rc.x, rc.y, pc.x, pc.y);
+                    const double fe = gflux(rc.y, re, pc.y, pe);
+                    double d0 = (fm - fw) * idx2, d1 = (fe - fm) * idx2;
+                    d0 += (gflux(rc.x, rn.x, pc.x, pn.x) - gflux(rs.x, rc.x, ps.x, pc.x)) * idy2;
+                    d1 += (gflux(rc.y, rn.y, pc.y, pn.y) - gflux(rs.y, rc.y, ps.y, pc.y)) * idy2;
+                    const double t0z = has_t ? gflux(rc.x, rtz.x, pc.x, ptz.x) * igt : 0.0;
+                    const double t1z = has_t ? gflux(rc.y, rtz.y, pc.y, ptz.y) * igt : 0.0;
+                    const double b0z = has_b ? gflux(rbz.x, rc.x, pbz.x, pc.x) * igb : 0.0;
+                    const double b1z = has_b ? gflux(rbz.y, rc.y, pbz.y, pc.y) * igb : 0.0;
+                    d0 += (t0z - b0z) * ih;
+                    d1 += (t1z - b1z) * ih;
+                    const double q0 = q.f.x - d0, q1 = q.f.y - d1;
+                    qabs += fabs(q0) + fabs(q1);
+                    v0 = rc.x * q0;
+                    v1 = rc.y * q1;
                 } else {  // residual r - mean - L p
                     double l0 = ((pc.y - pc.x) - (pc.x - pw)) * idx2;
                     double l1 = ((pe - pc.y) - (pc.y - pc.x)) * idx2;
@@ -223,6 +254,11 @@ __device__ __forceinline__ void fwd_x_tile(const XGeom& g, const Stencil& st, co
             rsum += v0 + v1;
             buf0[line * M + n] = C{(TC)v0, (TC)v1};
         }
+    }
+    if (MODE == FWD_METHOD3 && a.partials_abs) {
+        const double s1 = block_sum(qabs, red);
+        if (threadIdx.x == 0) a.partials_abs[b] = s1;
+        __syncthreads();
     }
     if (MODE != FWD_RESID && a.partials) {
         // FP64 volume-weighted sum of the right-hand side (its mean is the

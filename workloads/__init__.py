@@ -21,7 +21,10 @@ fields are not published, so these stand in for them):
 
 Seeds are ``numpy.random.default_rng([200511806, config, problem, stream])``
 with streams 0 = face field, 1 = spheres, 2 = temperature, 3 = p_prev,
-4 = w, 5 = grid draw, 6 = finite-difference directions.
+4 = w, 5 = grid draw, 6 = finite-difference directions, 7 = target
+divergence (Method III inputs: the face field is u*, the target divergence is
+N(0,1) noise weighted by the gas colour with its volume-weighted mean
+removed, so that a closed domain can meet it).
 """
 from __future__ import annotations
 
@@ -31,9 +34,10 @@ import numpy as np
 SEED_ROOT = 200511806
 RHO_LIQUID = 1000.0
 
-STREAM_FACES, STREAM_SPHERES, STREAM_TEMP, STREAM_PPREV, STREAM_W, STREAM_GRID, STREAM_FD = range(7)
+(STREAM_FACES, STREAM_SPHERES, STREAM_TEMP, STREAM_PPREV, STREAM_W, STREAM_GRID, STREAM_FD,
+ STREAM_DIVT) = range(8)
 
-CONFIG_IDS = {"const32": 0, "vd128": 1, "mixed_tanh": 2, "batch": 3, "grad256": 4}
+CONFIG_IDS = {"const32": 0, "vd128": 1, "mixed_tanh": 2, "batch": 3, "grad256": 4, "method3": 5}
 
 BATCH_SHAPES = ((64, 64, 64), (96, 96, 128), (128, 128, 128), (128, 128, 192))
 
@@ -251,6 +255,40 @@ def batch(n_problems: int = 64, shapes=BATCH_SHAPES) -> list:
     for p, (nx, ny, nz) in enumerate(batch_shapes(n_problems, shapes)):
         out.append(two_phase_case(f"batch{p}", uniform_grid(nx, ny, nz), 3, p, 20, 1))
     return out
+
+
+@dataclasses.dataclass
+class Method3Case:
+    """Inputs of a Method-III solve: ``base.faces`` is the predicted velocity
+    u*, ``div_target`` the target divergence, ``dt`` the time step; the
+    density comes from ``base`` as for Method I."""
+
+    base: Case
+    div_target: np.ndarray
+    dt: float
+
+
+def target_divergence(g: GridSpec, phi: np.ndarray, r: np.random.Generator,
+                      scale: float = 1.0) -> np.ndarray:
+    """scale * Phi * N(0,1), minus its volume-weighted mean."""
+    d = scale * phi * r.standard_normal((g.nz, g.ny, g.nx))
+    h = np.diff(g.z_faces())
+    v = np.broadcast_to(h[:, None, None], d.shape)
+    return d - (v * d).sum() / v.sum()
+
+
+def method3_case(name: str, g: GridSpec, problem: int = 0, n_spheres: int = 20,
+                 dt: float = 1e-3, rho_liq: float = 10.0) -> Method3Case:
+    """Two-phase Method-III inputs; the liquid density defaults to 10 (density
+    ratio up to 10 against gas at 1-5), the rising-bubble ratio."""
+    base = dataclasses.replace(two_phase_case(name, g, CONFIG_IDS["method3"], problem, n_spheres),
+                               rho_liq=rho_liq)
+    dtg = target_divergence(g, base.phi, rng(CONFIG_IDS["method3"], problem, STREAM_DIVT))
+    return Method3Case(base, dtg, dt)
+
+
+def method3_128(n: int = 128) -> Method3Case:
+    return method3_case("method3_128", uniform_grid(n, n, n), 0, 20)
 
 
 def fd_directions(config: int, n_dirs: int, shape) -> np.ndarray:
