@@ -358,42 +358,41 @@ psv_status psv_solve_method3(psv_plan* plan, const double* ux, const double* uy,
         const int nb = psv::fwd_x_blocks(P);
         double* qpart = P.partials + nb;  // sum |f - D(rho_f^-1 G p)| per block
         const double inv_scale = 2.0 / ((double)P.nx * P.ny);
-        int iters = 0;
-        bool converged = false;
-        double eps = NAN;
-        for (;;) {
-            psv::FwdArgs a{};
-            a.mode = psv::FWD_METHOD3;
-            a.f = f;
-            a.rho = rho;
-            a.pprev = has_p ? p_out : nullptr;
-            a.partials_abs = qpart;
-            psv::launch_fwd_x(P, fp32, a, s);
-            psv::launch_sum_partials(P, qpart, nb, P.scal + (has_p ? psv::S_EPS : psv::S_EPS0), s);
-            if (has_p) {
-                // the residual of the current iterate decides before solving again
-                sync_read(P, s);
-                eps = dt * P.host_scal[psv::S_EPS];
-                if (!std::isfinite(eps)) psv::fail(PSV_ERR_NONFINITE, "Method III residual is not finite");
-                if (eps <= eps_t) {
-                    converged = true;
-                    break;
-                }
-                if (iters >= max_iter) break;
+        const int* done = P.flags + psv::F_DONE;
+        // The residual of each iterate is tested on the device before the next
+        // solve; launches after convergence (or after max_iter solves) return at
+        // once. The host looks at the flag every few iterations.
+        constexpr int ITER_PER_SYNC = 4;
+        psv::launch_m3_reset(P, s);
+        for (int launched = 0;;) {
+            for (int b = 0; b < ITER_PER_SYNC; ++b, ++launched) {
+                psv::FwdArgs a{};
+                a.mode = psv::FWD_METHOD3;
+                a.f = f;
+                a.rho = rho;
+                a.pprev = has_p ? p_out : nullptr;
+                a.partials_abs = qpart;
+                a.done = done;
+                psv::launch_fwd_x(P, fp32, a, s);
+                psv::launch_m3_check(P, qpart, nb, dt, eps_t, has_p, max_iter, s);
+                psv::launch_z_solve(P, fp32, P.scal + psv::S_MEAN2, done, s);
+                psv::launch_inv_x(P, fp32, has_p ? psv::INV_ADD : psv::INV_STORE, p_out, inv_scale,
+                                  done, s);
+                has_p = true;
             }
-            psv::launch_z_solve(P, fp32, P.scal + psv::S_MEAN2, nullptr, s);
-            psv::launch_inv_x(P, fp32, has_p ? psv::INV_ADD : psv::INV_STORE, p_out, inv_scale,
-                              nullptr, s);
-            has_p = true;
-            ++iters;
+            sync_read(P, s);
+            if (P.host_flags[psv::F_DONE]) break;
+            if (!std::isfinite(P.host_scal[psv::S_EPS]))
+                psv::fail(PSV_ERR_NONFINITE, "Method III residual is not finite");
+            if (launched > max_iter + 1) psv::fail(PSV_ERR_HIP, "Method III loop control failed");
         }
         if (want_u) psv::launch_correct_velocity(P, ux, uy, uz, p_out, rho, dt, ux_out, uy_out, uz_out, s);
         if (info) {
             sync_read(P, s);
-            info->iterations = iters;
-            info->converged = converged ? 1 : 0;
-            info->eps = eps;
-            info->eps_start = p_init ? NAN : dt * P.host_scal[psv::S_EPS0];
+            info->iterations = P.host_flags[psv::F_STEPS];
+            info->converged = P.host_flags[psv::F_CONV];
+            info->eps = P.host_scal[psv::S_EPS];
+            info->eps_start = p_init ? NAN : P.host_scal[psv::S_EPS0];
         }
     });
 }

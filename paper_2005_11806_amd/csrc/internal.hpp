@@ -65,7 +65,7 @@ enum Scalar : int {
     S_EPS0 = 8,        // Method III: the same for p = 0 (u = u*)
     S_NSCAL = 16
 };
-enum Flag : int { F_DONE = 0, F_ARGMIN = 1, F_STEPS = 2, F_NFLAG = 8 };
+enum Flag : int { F_DONE = 0, F_ARGMIN = 1, F_STEPS = 2, F_CONV = 3, F_NFLAG = 8 };
 
 struct DevTables {
     // twiddles exp(-2 pi i t / n)
@@ -208,6 +208,14 @@ void launch_correct_velocity(const Plan& p, const double* ux, const double* uy, 
 // out = sum of partials[0 .. nblocks)
 void launch_sum_partials(const Plan& p, const double* partials, int nblocks, double* out,
                          hipStream_t s);
+// Method III loop control on the device: clear the loop flags; after each
+// forward pass, eps = dt * sum(partials) goes to S_EPS (S_EPS0 without a
+// pressure iterate); flags[F_DONE] is set once eps <= eps_t (F_CONV too) or
+// once max_iter solves were launched, else flags[F_STEPS] counts the solve
+// that follows. Nothing changes once F_DONE is set.
+void launch_m3_reset(const Plan& p, hipStream_t s);
+void launch_m3_check(const Plan& p, const double* partials, int nblocks, double dt, double eps_t,
+                     bool has_p, int max_iter, hipStream_t s);
 void launch_adjoint_faces(const Plan& p, const double* x, const double* f, const double* rho,
                           const double* pprev, const double* rho0, double* grad_f,
                           double* grad_rho, double* grad_p, double* partials, hipStream_t s);

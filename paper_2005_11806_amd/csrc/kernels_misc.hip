@@ -115,6 +115,40 @@ __global__ void k_relres_final(double* scal, int* flags, double tol) {
     }
 }
 
+__global__ void k_m3_reset(int* flags) {
+    if (threadIdx.x == 0) {
+        flags[F_DONE] = 0;
+        flags[F_STEPS] = 0;
+        flags[F_CONV] = 0;
+    }
+}
+
+__global__ void __launch_bounds__(RB) k_m3_check(const double* partials, int nb, double dt,
+                                                 double eps_t, int has_p, int max_iter,
+                                                 double* scal, int* flags) {
+    __shared__ double sh[16];
+    if (flags[F_DONE]) return;  // uniform over the block
+    double v = 0.0;
+    for (int b = threadIdx.x; b < nb; b += RB) v += partials[b];
+    const double eps = dt * block_sum(v, sh);
+    if (threadIdx.x != 0) return;
+    if (!has_p) {
+        scal[S_EPS0] = eps;
+    } else {
+        scal[S_EPS] = eps;
+        if (eps <= eps_t) {
+            flags[F_CONV] = 1;
+            flags[F_DONE] = 1;
+            return;
+        }
+        if (flags[F_STEPS] >= max_iter) {
+            flags[F_DONE] = 1;
+            return;
+        }
+    }
+    flags[F_STEPS] += 1;
+}
+
 __global__ void k_set_scalar(double* dst, double v) {
     if (threadIdx.x == 0) *dst = v;
 }
@@ -455,6 +489,18 @@ void launch_correct_velocity(const Plan& p, const double* ux, const double* uy, 
     TraceScope ts(p, "correct_velocity", s);
     hipLaunchKernelGGL(k_correct_velocity, dim3(nb), dim3(RB), 0, s, make_geo(p), ux, uy, uz, pr,
                        rho, dt, ox, oy, oz);
+    PSV_HIP(hipGetLastError());
+}
+
+void launch_m3_reset(const Plan& p, hipStream_t s) {
+    hipLaunchKernelGGL(k_m3_reset, dim3(1), dim3(64), 0, s, p.flags);
+    PSV_HIP(hipGetLastError());
+}
+
+void launch_m3_check(const Plan& p, const double* partials, int nblocks, double dt, double eps_t,
+                     bool has_p, int max_iter, hipStream_t s) {
+    hipLaunchKernelGGL(k_m3_check, dim3(1), dim3(RB), 0, s, partials, nblocks, dt, eps_t,
+                       has_p ? 1 : 0, max_iter, p.scal, p.flags);
     PSV_HIP(hipGetLastError());
 }
 
