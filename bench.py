@@ -90,6 +90,10 @@ def kernel_bytes(name, nx, ny, nz, kc=None):
         return 8 * n
     if name == "residual_fp64":
         return 2 * 8 * n
+    if name == "adjoint_faces":
+        return 4 * 8 * n + 2 * 8 * n  # x, f, rho, p_prev in; grad_f, grad_rho out
+    if name == "correct_velocity":
+        return 5 * 8 * n + 3 * 8 * n  # u* (3), p, rho in; u (3) out
     return None
 
 
@@ -311,6 +315,69 @@ def bench_method3(args):
     print(json.dumps(line), flush=True)
 
 
+GRAD_WORKLOADS = {
+    "grad256": ("fp64", "256^3 two-phase Method-I step, forward solve + hand-written adjoint "
+                "(grad_f, grad_rho with rho0 = min rho routed to its argmin), FP64"),
+    "grad256_mixed": ("mixed", "same forward + adjoint with FP32 solves and FP64 refinement"),
+}
+
+
+def bench_grad(args):
+    """Forward + adjoint pairs per second on the 256^3 two-phase step."""
+    import torch
+    import paper_2005_11806_amd as psv
+    import workloads as W
+    prec, desc = GRAD_WORKLOADS[args.workload]
+    case = W.grad256()
+    spec = case.grid
+    dev = torch.device("cuda:0")
+    to = lambda a: torch.from_numpy(a).to(dev)  # noqa: E731
+    plan = psv.Plan(psv.Grid.from_spec(spec), precision=prec, autotune=args.autotune)
+    f = plan.divergence(*(to(u) for u in case.faces))
+    rho = plan.density_from_colour(to(case.phi), to(case.rho_gas), case.rho_liq)
+    pp, w = to(case.p_prev), to(case.w)
+    out = torch.empty(spec.nz, spec.ny, spec.nx, dtype=torch.float64, device=dev)
+
+    def step():
+        plan.solve(f, rho=rho, p_prev=pp, out=out)
+        return plan.adjoint(w, f=f, rho=rho, p_prev=pp)
+
+    for _ in range(max(args.warmup, 1)):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    plan.trace(True)
+    step()
+    torch.cuda.synchronize()
+    summary = plan.trace_summary()
+    plan.trace(False)
+    dom = max(summary, key=lambda k: summary[k][1])
+    launches, total_ms = summary[dom]
+    avg_s = total_ms / launches * 1e-3
+    kc = plan.launch_shape()[1]
+    alg = kernel_bytes(dom, spec.nx, spec.ny, spec.nz, kc)
+    ach = alg / avg_s / 1e9 if alg else None
+    line = {
+        "metric": METRIC, "value": spec.n * args.steps / el, "unit": "grid_pts/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * el / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if prec == "fp64" else "f32+f64",
+        "data": "synthetic (seeded generators in workloads/)",
+        "config": {"workload": f"{args.workload}: {desc}", "grid": [spec.nx, spec.ny, spec.nz]},
+        "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": ach / HBM_PEAK_GBS if ach else None, "traffic": None, "kernel": dom,
+                     "avg_launch_us": avg_s * 1e6, "algorithmic_bytes": alg, "chunk_rows": kc,
+                     "kernels": {k: kernel_row(k, v, spec, kc) for k, v in
+                                 sorted(summary.items(), key=lambda kv: -kv[1][1])}},
+        "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def bench_batch(args):
     """Throughput of the 64-problem uneven batch (total grid points per second)."""
     import torch
@@ -382,7 +449,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="vd128",
-                    choices=sorted(WORKLOADS) + sorted(BATCH_WORKLOADS) + sorted(METHOD3_WORKLOADS))
+                    choices=sorted(WORKLOADS) + sorted(BATCH_WORKLOADS) + sorted(METHOD3_WORKLOADS)
+                    + sorted(GRAD_WORKLOADS))
     ap.add_argument("--mode", default="graph", choices=["graph", "eager"])
     ap.add_argument("--autotune", type=int, default=1, choices=[0, 1],
                     help="tune launch shapes at plan creation (outside the timed region)")
@@ -409,6 +477,9 @@ def main():
         return
     if args.workload in METHOD3_WORKLOADS:
         bench_method3(args)
+        return
+    if args.workload in GRAD_WORKLOADS:
+        bench_grad(args)
         return
 
     if args.copy_probe:

@@ -4,6 +4,8 @@
 // face terms of the adjoint of one Method-I step.
 // Reductions are two-stage (per-block partials, then one block) so that
 // their results do not depend on scheduling.
+#include <algorithm>
+
 #include "internal.hpp"
 
 namespace psv {
@@ -161,13 +163,6 @@ struct Geo {
     const double* vol;
 };
 
-__device__ __forceinline__ void cell_coords(size_t c, const Geo& g, int& i, int& j, int& k) {
-    i = (int)(c % g.nx);
-    const size_t q = c / g.nx;
-    j = (int)(q % g.ny);
-    k = (int)(q / g.ny);
-}
-
 // res = r - mean - L p ; partial sums of res^2 and (r - mean)^2. One thread
 // per pair of cells (2q, 2q+1) of an x-line (nx is even), 16-byte loads,
 // 32-bit index arithmetic (every index is below nx ny nz < 2^31).
@@ -309,31 +304,30 @@ struct AdjArgs {
 
 __global__ void __launch_bounds__(RB) k_adjoint_faces(Geo g, AdjArgs a) {
     __shared__ double sh[16];
-    const size_t n = (size_t)g.nx * g.ny * g.nz;
-    const size_t plane = (size_t)g.nx * g.ny;
+    const unsigned nx = (unsigned)g.nx, ny = (unsigned)g.ny, nz = (unsigned)g.nz;
+    const unsigned plane = nx * ny, n = plane * nz;  // every index is below 2^31
     const double rho0 = *a.rho0p;
     double acc = 0.0;
-    for (size_t c = (size_t)blockIdx.x * RB + threadIdx.x; c < n; c += (size_t)gridDim.x * RB) {
-        int i, j, k;
-        cell_coords(c, g, i, j, k);
-        const size_t row = c - i;
+    for (unsigned c = blockIdx.x * RB + threadIdx.x; c < n; c += gridDim.x * RB) {
+        unsigned i, j, k;
+        cell_ijk(c, g, i, j, k);
         const double lc = g.vol[k] * a.x[c], rc = a.rho[c], pc = a.pp[c];
         const double ihc = g.inv_h[k];
         double gr = 0.0, gp = 0.0;
         // neighbour offsets: east, west, north, south, top, bottom
-        size_t nb[6];
-        bool has[6] = {true, true, true, true, k + 1 < g.nz, k > 0};
-        nb[0] = row + (i + 1 == g.nx ? 0 : i + 1);
-        nb[1] = row + (i == 0 ? g.nx - 1 : i - 1);
-        nb[2] = c - (size_t)j * g.nx + (size_t)(j + 1 == g.ny ? 0 : j + 1) * g.nx;
-        nb[3] = c - (size_t)j * g.nx + (size_t)(j == 0 ? g.ny - 1 : j - 1) * g.nx;
+        unsigned nb[6];
+        bool has[6] = {true, true, true, true, k + 1 < nz, k > 0};
+        nb[0] = i + 1 == nx ? c + 1 - nx : c + 1;
+        nb[1] = i == 0 ? c + nx - 1 : c - 1;
+        nb[2] = j + 1 == ny ? c + nx - plane : c + nx;
+        nb[3] = j == 0 ? c + plane - nx : c - nx;
         nb[4] = has[4] ? c + plane : c;
         nb[5] = has[5] ? c - plane : c;
 #pragma unroll
         for (int q = 0; q < 6; ++q) {
             if (!has[q]) continue;
-            const size_t o = nb[q];
-            const int ko = (q == 4) ? k + 1 : (q == 5 ? k - 1 : k);
+            const unsigned o = nb[q];
+            const unsigned ko = (q == 4) ? k + 1 : (q == 5 ? k - 1 : k);
             const double lo = g.vol[ko] * a.x[o], ro = a.rho[o], po = a.pp[o];
             // plus faces (q even): c is the left cell; minus faces: c is the right cell
             const bool plus = (q & 1) == 0;
@@ -344,12 +338,12 @@ __global__ void __launch_bounds__(RB) k_adjoint_faces(Geo g, AdjArgs a) {
             const double ihl = (q < 4) ? ihc_o : ihc;  // own width in this direction
             const double dt = plus ? (lc * ihl - lo * ihc_o) : (lo * ihc_o - lc * ihl);
             const double gpf = plus ? (po - pc) * inv_d : (pc - po) * inv_d;
-            const double rf = 0.5 * (rc + ro);
+            const double irf = 2.0 * rcp_nr(rc + ro);  // 1 / rho_f
             const double gf = dt * gpf;
-            gr += 0.5 * gf * rho0 / (rf * rf);
-            const double bdt = (1.0 - rho0 / rf) * dt;
+            gr += 0.5 * gf * rho0 * irf * irf;
+            const double bdt = (1.0 - rho0 * irf) * dt;
             gp += plus ? -bdt * inv_d : bdt * inv_d;
-            if (plus) acc -= gf / rf;
+            if (plus) acc -= gf * irf;
         }
         acc += lc * (a.f ? a.f[c] : 0.0);
         if (a.grad_f) a.grad_f[c] = rho0 * lc;
@@ -361,20 +355,17 @@ __global__ void __launch_bounds__(RB) k_adjoint_faces(Geo g, AdjArgs a) {
 }
 
 __global__ void k_scale_vol(Geo g, const double* __restrict__ x, double* __restrict__ out) {
-    const size_t n = (size_t)g.nx * g.ny * g.nz;
-    const size_t plane = (size_t)g.nx * g.ny;
-    for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < n;
-         c += (size_t)gridDim.x * blockDim.x)
+    const unsigned plane = (unsigned)g.nx * (unsigned)g.ny, n = plane * (unsigned)g.nz;
+    for (unsigned c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x)
         out[c] = g.vol[c / plane] * x[c];
 }
 
 // partial sums of vol[k] r[c] (volume-weighted integral)
 __global__ void __launch_bounds__(RB) k_vsum(Geo g, const double* __restrict__ r, double* partials) {
     __shared__ double sh[16];
-    const size_t n = (size_t)g.nx * g.ny * g.nz;
-    const size_t plane = (size_t)g.nx * g.ny;
+    const unsigned plane = (unsigned)g.nx * (unsigned)g.ny, n = plane * (unsigned)g.nz;
     double acc = 0.0;
-    for (size_t c = (size_t)blockIdx.x * RB + threadIdx.x; c < n; c += (size_t)gridDim.x * RB)
+    for (unsigned c = blockIdx.x * RB + threadIdx.x; c < n; c += gridDim.x * RB)
         acc += g.vol[c / plane] * r[c];
     const double s = block_sum(acc, sh);
     if (threadIdx.x == 0) partials[blockIdx.x] = s;
@@ -426,7 +417,8 @@ int grid_blocks(size_t n, int thr) {
 
 }  // namespace
 
-int adjoint_blocks(const Plan& p) { return grid_blocks(p.ncell(), RB); }
+// up to 4096 blocks (the plan's partials hold at least 8192 values)
+int adjoint_blocks(const Plan& p) { return (int)std::min<size_t>(4096, (p.ncell() + RB - 1) / RB); }
 
 void launch_min_reduce(const Plan& p, const double* x, double* out_scalar, int* argmin_out,
                        hipStream_t s) {
@@ -514,6 +506,7 @@ void launch_adjoint_faces(const Plan& p, const double* x, const double* f, const
                           const double* pprev, const double* rho0, double* grad_f,
                           double* grad_rho, double* grad_p, double* partials, hipStream_t s) {
     AdjArgs a{x, f, rho, pprev, rho0, grad_f, grad_rho, grad_p, partials};
+    TraceScope ts(p, "adjoint_faces", s);
     hipLaunchKernelGGL(k_adjoint_faces, dim3(adjoint_blocks(p)), dim3(RB), 0, s, make_geo(p), a);
     PSV_HIP(hipGetLastError());
 }
