@@ -46,7 +46,7 @@ extern "C" {
 typedef enum {
     PSV_OK = 0,
     PSV_ERR_INVALID_ARG = 1,      /* bad pointer, size, option or input value */
-    PSV_ERR_UNSUPPORTED_SIZE = 2, /* nx or ny not even or not 2^a 3^b, or too large */
+    PSV_ERR_UNSUPPORTED_SIZE = 2, /* nx or ny (other than ny = 1) not even or not 2^a 3^b, or too large */
     PSV_ERR_HIP = 3,              /* a HIP runtime call failed */
     PSV_ERR_NONFINITE = 4,        /* check_inputs found NaN/Inf in an input */
     PSV_ERR_NOT_CONVERGED = 5,    /* mixed precision hit max_refine; p holds the last iterate */
@@ -63,7 +63,8 @@ typedef enum {
 typedef enum { PSV_BC_WALL_NEUMANN = 0 } psv_bc_z;
 
 /* Grid (Sec. 3). x and y periodic with nx, ny even and of the form 2^a 3^b,
- * 4 <= nx, ny <= 1024; nz >= 2. zf: HOST array of nz+1 strictly increasing
+ * 4 <= nx, ny <= 1024, or ny = 1 for a two-dimensional x-z problem (the
+ * paper's own cases); nz >= 2. zf: HOST array of nz+1 strictly increasing
  * z-face positions with zf[0] = 0 and zf[nz] = lz (copied at plan creation),
  * or NULL for uniform spacing lz/nz. Cell centres are face midpoints. */
 typedef struct {

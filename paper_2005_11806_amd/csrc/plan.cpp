@@ -47,10 +47,11 @@ void validate_grid(const psv_grid* g) {
     if (g->bc_z != PSV_BC_WALL_NEUMANN) fail(PSV_ERR_INVALID_ARG, "unknown z boundary condition");
     if (g->nz < 2) fail(PSV_ERR_INVALID_ARG, "nz must be >= 2");
     if (g->nz > 2048) fail(PSV_ERR_UNSUPPORTED_SIZE, "nz must be <= 2048");
-    for (int n : {g->nx, g->ny}) {
-        if (n < 4 || n > 1024 || (n & 1) || !is_23_smooth(n))
-            fail(PSV_ERR_UNSUPPORTED_SIZE, "nx and ny must be even, of the form 2^a 3^b, in [4, 1024]");
-    }
+    // ny = 1 is a two-dimensional x-z problem (one periodic cell in y: no y fluxes)
+    auto size_ok = [](int n) { return n >= 4 && n <= 1024 && !(n & 1) && is_23_smooth(n); };
+    if (!size_ok(g->nx) || !(g->ny == 1 || size_ok(g->ny)))
+        fail(PSV_ERR_UNSUPPORTED_SIZE,
+             "nx and ny must be even, of the form 2^a 3^b, in [4, 1024] (or ny = 1)");
     if (!(g->lx > 0) || !(g->ly > 0) || !(g->lz > 0) || !std::isfinite(g->lx) ||
         !std::isfinite(g->ly) || !std::isfinite(g->lz))
         fail(PSV_ERR_INVALID_ARG, "domain lengths must be positive and finite");

@@ -49,6 +49,10 @@ def _status(g):
     (2048, 32, 32, _abi.PSV_ERR_UNSUPPORTED_SIZE),  # too large
     (32, 32, 1, _abi.PSV_ERR_INVALID_ARG),          # nz < 2
     (32, 32, 4096, _abi.PSV_ERR_UNSUPPORTED_SIZE),
+    (128, 1, 256, _abi.PSV_OK),                     # two-dimensional x-z problem
+    (1, 32, 32, _abi.PSV_ERR_UNSUPPORTED_SIZE),     # only y may be a single cell
+    (1, 1, 32, _abi.PSV_ERR_UNSUPPORTED_SIZE),
+    (32, 2, 32, _abi.PSV_ERR_UNSUPPORTED_SIZE),
 ])
 def test_grid_validation(nx, ny, nz, code):
     assert _status(psv.Grid(nx, ny, nz)) == code

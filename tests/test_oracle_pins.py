@@ -317,3 +317,17 @@ def test_adjoint_dot_product_identity():
     res = oadj.adjoint_step(w, f, rho, rho0, pp, g)
     jv = O.solve_const(rho0 * v, g)[0]
     assert np.isclose((w * jv).sum(), (res.grad_f * v).sum(), rtol=1e-11)
+
+
+@pytest.mark.parametrize("stretched", [False, True])
+def test_two_dimensional_solve_matches_dense(stretched):
+    """ny = 1 (one periodic cell in y, the paper's two-dimensional cases):
+    the eigenexpansion solve equals dense bordered LU of the 5-point x-z
+    operator, and the y fluxes vanish."""
+    g = O.Grid(12, 1, 7, 1.0, 0.4, 1.3, W.tanh_faces(7, 1.3, 1.5) if stretched else None)
+    f = _rng(40).standard_normal(g.shape)
+    p, _ = O.solve_const(f, g)
+    pd, _ = dense.bordered_solve(dense.laplacian_matrix(g), f, dense.volume_vector(g))
+    assert np.abs(p.ravel() - pd).max() <= 1e-12 * np.abs(pd).max()
+    gx, gy, gz = O.grad(p, g)
+    assert np.all(gy == 0.0)
