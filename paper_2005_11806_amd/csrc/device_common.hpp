@@ -187,13 +187,24 @@ __host__ __device__ constexpr int radix_prefix(RadixList L, int s) {
     return p;
 }
 
+// LDS layouts of FFT lines: contiguous, or with one pad element after every 8
+// (the radix-R scatter of a Stockham stage then spreads over the banks
+// instead of hitting the same ones); element i lives at at(i).
+struct NoPad {
+    __device__ static constexpr int at(int i) { return i; }
+};
+struct Pad8 {
+    __device__ static constexpr int at(int i) { return i + (i >> 3); }
+};
+
 // Butterfly j of a radix-R Stockham stage (NS = product of the earlier
-// radices, NB = N / R): load with twiddles and transform into v, then store.
-template <int R, int DIR, int NS, int NB, int TSTEP, typename C>
+// radices, NB = N / R) of the line starting at element off: load with
+// twiddles and transform into v, then store.
+template <int R, int DIR, int NS, int NB, int TSTEP, typename P = NoPad, typename C>
 __device__ __forceinline__ void stockham_load_ct(const C* __restrict__ in, int j,
-                                                 const C* __restrict__ tw, C* v) {
+                                                 const C* __restrict__ tw, C* v, int off = 0) {
 #pragma unroll
-    for (int r = 0; r < R; ++r) v[r] = in[j + r * NB];
+    for (int r = 0; r < R; ++r) v[r] = in[P::at(off + j + r * NB)];
     const int k = j % NS;
     if (NS > 1) {
 #pragma unroll
@@ -209,11 +220,12 @@ __device__ __forceinline__ void stockham_load_ct(const C* __restrict__ in, int j
     if (R == 8) bfly8<DIR>(v);
 }
 
-template <int R, int NS, typename C>
-__device__ __forceinline__ void stockham_store_ct(C* __restrict__ out, int j, const C* v) {
-    const int base = (j / NS) * NS * R + j % NS;
+template <int R, int NS, typename P = NoPad, typename C>
+__device__ __forceinline__ void stockham_store_ct(C* __restrict__ out, int j, const C* v,
+                                                  int off = 0) {
+    const int base = off + (j / NS) * NS * R + j % NS;
 #pragma unroll
-    for (int r = 0; r < R; ++r) out[base + r * NS] = v[r];
+    for (int r = 0; r < R; ++r) out[P::at(base + r * NS)] = v[r];
 }
 
 template <int R, int DIR, int NS, int NB, int TSTEP, typename C>
@@ -246,11 +258,11 @@ __device__ __forceinline__ C* fft_stages(C* src, C* dst, int nlines, int lstride
     }
 }
 
-// In-place variant for NL lines of length N stored contiguously in one LDS
-// buffer: every stage reads all of its butterflies into registers (a thread
-// takes butterflies t, t + 256, ...), waits for the block, then writes. Ends
-// with the block synchronised.
-template <int N, int S, int DIR, int TWM, int NL, typename C>
+// In-place variant for NL lines of length N stored one after the other in
+// one LDS buffer in layout P: every stage reads all of its butterflies into
+// registers (a thread takes butterflies t, t + 256, ...), waits for the block,
+// then writes. Ends with the block synchronised.
+template <int N, int S, int DIR, int TWM, int NL, typename P = NoPad, typename C>
 __device__ __forceinline__ void fft_inplace(C* buf, const C* __restrict__ tw) {
     constexpr RadixList RL = radix_list(N);
     if constexpr (S < RL.count) {
@@ -266,7 +278,7 @@ __device__ __forceinline__ void fft_inplace(C* buf, const C* __restrict__ tw) {
             const int t = (int)threadIdx.x + it * 256;
             if (TOTAL % 256 == 0 || t < TOTAL) {
                 const int line = t / NB;
-                stockham_load_ct<R, DIR, NS, NB, TSTEP>(buf + line * N, t - line * NB, tw, v[it]);
+                stockham_load_ct<R, DIR, NS, NB, TSTEP, P>(buf, t - line * NB, tw, v[it], line * N);
             }
         }
         __syncthreads();
@@ -275,11 +287,11 @@ __device__ __forceinline__ void fft_inplace(C* buf, const C* __restrict__ tw) {
             const int t = (int)threadIdx.x + it * 256;
             if (TOTAL % 256 == 0 || t < TOTAL) {
                 const int line = t / NB;
-                stockham_store_ct<R, NS>(buf + line * N, t - line * NB, v[it]);
+                stockham_store_ct<R, NS, P>(buf, t - line * NB, v[it], line * N);
             }
         }
         __syncthreads();
-        fft_inplace<N, S + 1, DIR, TWM, NL>(buf, tw);
+        fft_inplace<N, S + 1, DIR, TWM, NL, P>(buf, tw);
     }
 }
 

@@ -46,11 +46,17 @@ inline bool yz_compiled(int ny) {
     }
 }
 
-// LDS of a y tile: kc lines (two buffers of them for a runtime length) and
-// the twiddle table
+// LDS of a y tile: kc lines (padded by one element per 8 for a compile-time
+// length; two plain buffers of them for a runtime length) and the twiddles
 inline size_t yz_lds(int ny, int kc, size_t csz) {
-    return ((size_t)(yz_compiled(ny) ? 1 : 2) * kc * ny + ny) * csz;
+    const size_t lines = yz_compiled(ny) ? (size_t)kc * ny + (size_t)kc * ny / 8 : (size_t)2 * kc * ny;
+    return (lines + ny) * csz;
 }
+
+// LDS layout of the tile's lines: padded for the compile-time lengths (all
+// multiples of 8), plain for the runtime FFT
+template <int N>
+using YzLayout = std::conditional_t<(N > 0), Pad8, NoPad>;
 
 struct ZArgs {
     int nz, mx, ny;
@@ -195,7 +201,7 @@ template <typename T, int N, int KC, int DIR>
 __device__ __forceinline__ c2<T>* yz_fft(c2<T>* buf, int ny, int nlines, const Radices& rad,
                                          const c2<T>* tw) {
     if constexpr (N > 0) {
-        fft_inplace<N, 0, DIR, 1, KC>(buf, tw);
+        fft_inplace<N, 0, DIR, 1, KC, YzLayout<N>>(buf, tw);
         return buf;
     } else {
         return lds_fft<DIR>(buf, buf + KC * ny, ny, nlines, ny, rad, tw, ny);
@@ -209,13 +215,20 @@ __device__ __forceinline__ void yz_load(const ZArgs& z, const c2<T>* __restrict_
                                         int nl, const c2<T>* __restrict__ tw_g, c2<T>* buf,
                                         c2<T>* tw) {
     using C = c2<T>;
+    using P = YzLayout<N>;
     const int ny = N ? N : z.ny;
     for (int t = threadIdx.x; t < ny; t += 256) tw[t] = tw_g[t];
     for (int e = threadIdx.x; e < KC * ny; e += 256) {
         const int i = e / ny, n = e - i * ny;
-        buf[e] = i < nl ? base[(size_t)i * SP + n] : C{(T)0, (T)0};
+        buf[P::at(e)] = i < nl ? base[(size_t)i * SP + n] : C{(T)0, (T)0};
     }
     __syncthreads();
+}
+
+// Number of buffer elements the tile's KC lines take in their layout.
+template <int N, int KC>
+__device__ __forceinline__ int yz_span(int ny) {
+    return N ? KC * N + KC * N / 8 : KC * ny;
 }
 
 // Forward y tile b = c mx + m (chunk c, wavenumber m): FFT along y of planes
@@ -226,9 +239,10 @@ __device__ __forceinline__ void yz_fwd_tile(const ZArgs& z, const Radices& rad,
                                             c2<T>* __restrict__ spec, const c2<T>* __restrict__ tw_g,
                                             int b, unsigned char* smem) {
     using C = c2<T>;
+    using P = YzLayout<N>;
     const int ny = N ? N : z.ny;
     C* buf = reinterpret_cast<C*>(smem);
-    C* tw = buf + (N ? 1 : 2) * KC * ny;  // exp(-2 pi i t / ny), t < ny
+    C* tw = buf + (N ? yz_span<N, KC>(ny) : 2 * KC * ny);  // exp(-2 pi i t / ny), t < ny
     const int c = b / z.mx, m = b - c * z.mx;
     const int k0 = c * KC;
     const int nl = min(KC, z.nz - k0);
@@ -238,12 +252,12 @@ __device__ __forceinline__ void yz_fwd_tile(const ZArgs& z, const Radices& rad,
     C* d = yz_fft<T, N, KC, -1>(buf, ny, KC, rad, tw);
     for (int n = threadIdx.x; n < ny; n += 256) {
         if (m == 0 && n == 0) continue;  // the (0,0) pair is solved apart
-        chunk_eliminate<T, KC>(z, k0, z.lamx[m] + z.lamy[n], d + n, ny);
+        chunk_eliminate<T, KC>(z, k0, z.lamx[m] + z.lamy[n], d + P::at(n), P::at(ny));
     }
     __syncthreads();
     for (int e = threadIdx.x; e < nl * ny; e += 256) {
         const int i = e / ny, n = e - i * ny;
-        base[(size_t)i * SP + n] = d[e];
+        base[(size_t)i * SP + n] = d[P::at(e)];
     }
 }
 
@@ -255,9 +269,10 @@ __device__ __forceinline__ void yz_inv_tile(const ZArgs& z, const Radices& rad,
                                             c2<T>* __restrict__ spec, const c2<T>* __restrict__ tw_g,
                                             int b, unsigned char* smem) {
     using C = c2<T>;
+    using P = YzLayout<N>;
     const int ny = N ? N : z.ny;
     C* buf = reinterpret_cast<C*>(smem);
-    C* tw = buf + (N ? 1 : 2) * KC * ny;
+    C* tw = buf + (N ? yz_span<N, KC>(ny) : 2 * KC * ny);
     const int c = b / z.mx, m = b - c * z.mx;
     const int k0 = c * KC;
     const int nl = min(KC, z.nz - k0);
@@ -266,13 +281,13 @@ __device__ __forceinline__ void yz_inv_tile(const ZArgs& z, const Radices& rad,
     yz_load<T, N, KC>(z, base, SP, nl, tw_g, buf, tw);
     for (int n = threadIdx.x; n < ny; n += 256) {
         if (m == 0 && n == 0) continue;
-        chunk_substitute<T, KC>(z, k0, nl, z.lamx[m] + z.lamy[n], buf + n, ny);
+        chunk_substitute<T, KC>(z, k0, nl, z.lamx[m] + z.lamy[n], buf + P::at(n), P::at(ny));
     }
     __syncthreads();
     C* r = yz_fft<T, N, KC, +1>(buf, ny, nl, rad, tw);
     for (int e = threadIdx.x; e < nl * ny; e += 256) {
         const int i = e / ny, n = e - i * ny;
-        base[(size_t)i * SP + n] = r[e];
+        base[(size_t)i * SP + n] = r[P::at(e)];
     }
 }
 
