@@ -244,6 +244,28 @@ BATCH_WORKLOADS = {
 }
 
 
+def traced_roofline(plan, step, spec):
+    """Runs one traced step and returns the roofline object of its dominant
+    kernel (per-kernel event timing on the plan's launch stream)."""
+    import torch
+    plan.trace(True)
+    step()
+    torch.cuda.synchronize()
+    summary = plan.trace_summary()
+    plan.trace(False)
+    dom = max(summary, key=lambda k: summary[k][1])
+    launches, total_ms = summary[dom]
+    avg_s = total_ms / launches * 1e-3
+    kc = plan.launch_shape()[1]
+    alg = kernel_bytes(dom, spec.nx, spec.ny, spec.nz, kc)
+    ach = alg / avg_s / 1e9 if alg else None
+    return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": ach / HBM_PEAK_GBS if ach else None, "traffic": None, "kernel": dom,
+            "avg_launch_us": avg_s * 1e6, "algorithmic_bytes": alg, "chunk_rows": kc,
+            "kernels": {k: kernel_row(k, v, spec, kc) for k, v in
+                        sorted(summary.items(), key=lambda kv: -kv[1][1])}}
+
+
 METHOD3_WORKLOADS = {
     "method3_128": ("fp64", "128^3 uniform, Method III with its loop (Algorithm 1), 20 spheres, "
                     "rho_l=10, rho_g=1-5, target divergence in the gas, dt=1e-3, to "
@@ -285,17 +307,6 @@ def bench_method3(args):
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     ms = 1e3 * el / args.steps
-    plan.trace(True)
-    step()
-    torch.cuda.synchronize()
-    summary = plan.trace_summary()
-    plan.trace(False)
-    dom = max(summary, key=lambda k: summary[k][1])
-    launches, total_ms = summary[dom]
-    avg_s = total_ms / launches * 1e-3
-    kc = plan.launch_shape()[1]
-    alg = kernel_bytes(dom, spec.nx, spec.ny, spec.nz, kc)
-    ach = alg / avg_s / 1e9 if alg else None
     line = {
         "metric": METRIC, "value": spec.n * args.steps / el, "unit": "grid_pts/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
@@ -305,11 +316,7 @@ def bench_method3(args):
                    "iterations": info.iterations, "converged": info.converged,
                    "eps": info.eps, "eps_start": info.eps_start,
                    "ms_per_iteration": ms / max(info.iterations, 1)},
-        "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": ach / HBM_PEAK_GBS if ach else None, "traffic": None, "kernel": dom,
-                     "avg_launch_us": avg_s * 1e6, "algorithmic_bytes": alg, "chunk_rows": kc,
-                     "kernels": {k: kernel_row(k, v, spec, kc) for k, v in
-                                 sorted(summary.items(), key=lambda kv: -kv[1][1])}},
+        "roofline": traced_roofline(plan, step, spec),
         "cpu_baseline": None,
     }
     print(json.dumps(line), flush=True)
@@ -350,17 +357,6 @@ def bench_grad(args):
         step()
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    plan.trace(True)
-    step()
-    torch.cuda.synchronize()
-    summary = plan.trace_summary()
-    plan.trace(False)
-    dom = max(summary, key=lambda k: summary[k][1])
-    launches, total_ms = summary[dom]
-    avg_s = total_ms / launches * 1e-3
-    kc = plan.launch_shape()[1]
-    alg = kernel_bytes(dom, spec.nx, spec.ny, spec.nz, kc)
-    ach = alg / avg_s / 1e9 if alg else None
     line = {
         "metric": METRIC, "value": spec.n * args.steps / el, "unit": "grid_pts/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * el / args.steps,
@@ -368,11 +364,68 @@ def bench_grad(args):
         "dtype": "f64" if prec == "fp64" else "f32+f64",
         "data": "synthetic (seeded generators in workloads/)",
         "config": {"workload": f"{args.workload}: {desc}", "grid": [spec.nx, spec.ny, spec.nz]},
-        "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": ach / HBM_PEAK_GBS if ach else None, "traffic": None, "kernel": dom,
-                     "avg_launch_us": avg_s * 1e6, "algorithmic_bytes": alg, "chunk_rows": kc,
-                     "kernels": {k: kernel_row(k, v, spec, kc) for k, v in
-                                 sorted(summary.items(), key=lambda kv: -kv[1][1])}},
+        "roofline": traced_roofline(plan, step, spec),
+        "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
+CONVERGED_WORKLOADS = {
+    "converged128": ("fp64", "method3", "128^3 uniform two-phase, 20 spheres, rho_l=10, rho_g=1-5: "
+                     "converged variable-density solve (weights rho) to eps <= 1e-10 eps(0), then "
+                     "its implicit adjoint (grad_f, grad_rho) to the same relative threshold; FP64"),
+    "converged128_mixed": ("mixed", "method3", "same forward + implicit adjoint with FP32 solves "
+                           "inside both loops"),
+    "converged128_method1": ("fp64", "method1", "same problem with the Method-I weight min rho "
+                             "in both loops; FP64"),
+}
+
+
+def bench_converged(args):
+    """Forward + implicit-adjoint pairs per second of the converged solve."""
+    import torch
+    import paper_2005_11806_amd as psv
+    import workloads as W
+    prec, iteration, desc = CONVERGED_WORKLOADS[args.workload]
+    case = W.converged_128()
+    spec = case.grid
+    dev = torch.device("cuda:0")
+    to = lambda a: torch.from_numpy(a).to(dev)  # noqa: E731
+    plan = psv.Plan(psv.Grid.from_spec(spec), precision=prec, autotune=args.autotune)
+    f = plan.divergence(*(to(u) for u in case.faces))
+    rho = plan.density_from_colour(to(case.phi), to(case.rho_gas), case.rho_liq)
+    w = to(case.w)
+    p = torch.empty(spec.nz, spec.ny, spec.nx, dtype=torch.float64, device=dev)
+    _, i0 = plan.solve_converged(f, rho, iteration=iteration, max_iter=1, out=p)
+    _, _, a0 = plan.converged_adjoint(w, rho, p, iteration=iteration, max_iter=1)
+    eps_f, eps_a = 1e-10 * i0.eps_start, 1e-10 * a0.eps_start
+
+    def step():
+        _, fi = plan.solve_converged(f, rho, iteration=iteration, eps_t=eps_f, max_iter=2000, out=p)
+        _, _, ai = plan.converged_adjoint(w, rho, p, iteration=iteration, eps_t=eps_a,
+                                          max_iter=2000)
+        return fi, ai
+
+    fi, ai = step()
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ms = 1e3 * el / args.steps
+    line = {
+        "metric": METRIC, "value": spec.n * args.steps / el, "unit": "grid_pts/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64" if prec == "fp64" else "f32+f64",
+        "data": "synthetic (seeded generators in workloads/)",
+        "config": {"workload": f"{args.workload}: {desc}", "grid": [spec.nx, spec.ny, spec.nz],
+                   "forward_iterations": fi.iterations, "adjoint_iterations": ai.iterations,
+                   "converged": fi.converged and ai.converged,
+                   "ms_per_iteration": ms / max(fi.iterations + ai.iterations, 1)},
+        "roofline": traced_roofline(plan, step, spec),
         "cpu_baseline": None,
     }
     print(json.dumps(line), flush=True)
@@ -450,7 +503,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="vd128",
                     choices=sorted(WORKLOADS) + sorted(BATCH_WORKLOADS) + sorted(METHOD3_WORKLOADS)
-                    + sorted(GRAD_WORKLOADS))
+                    + sorted(GRAD_WORKLOADS) + sorted(CONVERGED_WORKLOADS))
     ap.add_argument("--mode", default="graph", choices=["graph", "eager"])
     ap.add_argument("--autotune", type=int, default=1, choices=[0, 1],
                     help="tune launch shapes at plan creation (outside the timed region)")
@@ -480,6 +533,9 @@ def main():
         return
     if args.workload in GRAD_WORKLOADS:
         bench_grad(args)
+        return
+    if args.workload in CONVERGED_WORKLOADS:
+        bench_converged(args)
         return
 
     if args.copy_probe:

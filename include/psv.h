@@ -181,6 +181,51 @@ psv_status psv_solve_method3(psv_plan* plan, const double* ux, const double* uy,
                              double* ux_out, double* uy_out, double* uz_out, void* stream,
                              psv_m3_info* info);
 
+/* The converged variable-density solve: the fixed point that Methods I and III
+ * both iterate towards (Sec. 3.3.1; Eq. lap_p with f given directly),
+ *     D(rho_f^-1 G p) = f - mean_V(f),
+ * reached by iterating, in pressure form,
+ *     p <- p + S[omega (f - mean_V(f) - D(rho_f^-1 G p))],
+ * S the plan's eigenexpansion solve, with omega = min rho (PSV_ITER_METHOD1:
+ * Eq. poisson_me1, robust at any density ratio, slow) or omega = rho in each
+ * cell (PSV_ITER_METHOD3: Eq. new_poisson, fewer iterations; may diverge at
+ * large density ratios on fine grids), until
+ *     eps = sum over cells of |f - mean_V(f) - D(rho_f^-1 G p)| <= eps_t
+ * or max_iter solves. mean_V is the volume-weighted mean.
+ *   f, rho [nz][ny][nx] device fields, rho > 0
+ *   p_init optional starting pressure (may equal p_out); p_out keeps its
+ *          volume-weighted mean (zero when p_init is NULL)
+ *   p_out  must not alias f or rho
+ * info (may be NULL; the call then does not synchronise at its end):
+ * iterations = solves performed, eps of the returned p, eps_start = eps of
+ * p = 0 (NaN when p_init is given). MIXED plans run FP32 solves inside the
+ * loop, which corrects them. Stops without error at max_iter
+ * (info->converged = 0). Synchronises every few iterations. */
+typedef enum { PSV_ITER_METHOD1 = 1, PSV_ITER_METHOD3 = 3 } psv_iteration;
+psv_status psv_solve_converged(psv_plan* plan, const double* f, const double* rho,
+                               int32_t iteration, double eps_t, int32_t max_iter,
+                               const double* p_init, double* p_out, void* stream,
+                               psv_m3_info* info);
+
+/* Implicit adjoint of psv_solve_converged for loss = sum(w * p): V A is
+ * symmetric (A = D(rho_f^-1 G), V the cell volumes), so the gradients take one
+ * more converged solve instead of differentiating the iterations:
+ *     lambda      = A^+ (V^-1 w), zero volume-weighted mean (same iteration,
+ *                   eps_t and max_iter; eps is measured on V^-1 w's system)
+ *     grad_f      = V lambda
+ *     grad_rho[c] = sum over the faces F of cell c of
+ *                   (D^T V lambda)_F (G p)_F / (2 rho_F^2),
+ * with (D^T mu)_F = mu_L/h_L - mu_R/h_R across F and rho_F the arithmetic
+ * mean of the two cells of F.
+ *   w, rho [nz][ny][nx]; p = the converged pressure of the forward call
+ *   (required for grad_rho). grad_f / grad_rho may be NULL to skip them; they
+ *   must not alias rho or p (grad_f may alias w). Uses the plan's workspace.
+ * info describes the adjoint solve. */
+psv_status psv_solve_converged_adjoint(psv_plan* plan, const double* w, const double* rho,
+                                       const double* p, int32_t iteration, double eps_t,
+                                       int32_t max_iter, double* grad_f, double* grad_rho,
+                                       void* stream, psv_m3_info* info);
+
 /* Mixture density of Sec. 2.2, Eq. eq_22, with the colour Phi = 1 in gas:
  * rho = rho_gas * Phi + rho_liq * (1 - Phi). phi and rho_gas are device fields. */
 psv_status psv_density_from_colour(const psv_plan* plan, const double* phi, const double* rho_gas,

@@ -19,8 +19,8 @@ import numpy as np
 from . import _abi
 from ._abi import PsvError, check
 
-__all__ = ["Grid", "Plan", "Batch", "SolveInfo", "PsvError", "lib", "PressureSolve",
-           "pressure_solve"]
+__all__ = ["Grid", "Plan", "Batch", "SolveInfo", "Method3Info", "PsvError", "lib",
+           "PressureSolve", "pressure_solve", "ConvergedSolve", "converged_solve"]
 
 
 def lib():
@@ -82,6 +82,13 @@ class Method3Info:
 
 _PREC = {"fp64": _abi.PSV_FP64, "mixed": _abi.PSV_MIXED}
 _METH = {"const": _abi.PSV_CONST, "method1": _abi.PSV_SPLIT_RHO0}
+_ITER = {"method1": _abi.PSV_ITER_METHOD1, "method3": _abi.PSV_ITER_METHOD3}
+
+
+def _iteration(name):
+    if name not in _ITER:
+        raise ValueError(f"iteration must be one of {sorted(_ITER)}, got {name!r}")
+    return _ITER[name]
 
 
 def _ptr(t, shape=None, name="tensor"):
@@ -223,6 +230,39 @@ class Plan:
             _ptr(uo[2], (nz + 1, ny, nx)) if uo else None, _stream(stream), C.byref(inf)))
         return out, uo, Method3Info(inf.iterations, bool(inf.converged), inf.eps, inf.eps_start)
 
+    def solve_converged(self, f, rho, iteration="method3", eps_t=0.0, max_iter=50, p_init=None,
+                        out=None, stream=None):
+        """Converged variable-density solve D(rho_f^-1 G p) = f - mean_V(f)
+        (psv_solve_converged). iteration: "method1" (weight min rho) or
+        "method3" (weight rho). Returns (p, Method3Info); eps is the summed
+        absolute residual of that equation."""
+        import torch
+        sh = self.shape
+        if out is None:
+            out = torch.empty(sh, dtype=torch.float64, device=f.device)
+        inf = _abi.psv_m3_info()
+        check(lib().psv_solve_converged(
+            self._h, _ptr(f, sh, "f"), _ptr(rho, sh, "rho"), _iteration(iteration), float(eps_t),
+            int(max_iter), _ptr(p_init, sh, "p_init"), _ptr(out, sh, "out"), _stream(stream),
+            C.byref(inf)))
+        return out, Method3Info(inf.iterations, bool(inf.converged), inf.eps, inf.eps_start)
+
+    def converged_adjoint(self, w, rho, p, iteration="method3", eps_t=0.0, max_iter=50,
+                          grad_f=True, grad_rho=True, stream=None):
+        """Implicit adjoint of solve_converged for loss = sum(w p)
+        (psv_solve_converged_adjoint). Returns (grad_f or None, grad_rho or
+        None, Method3Info of the adjoint solve)."""
+        import torch
+        sh = self.shape
+        gf = torch.empty(sh, dtype=torch.float64, device=w.device) if grad_f else None
+        gr = torch.empty(sh, dtype=torch.float64, device=w.device) if grad_rho else None
+        inf = _abi.psv_m3_info()
+        check(lib().psv_solve_converged_adjoint(
+            self._h, _ptr(w, sh, "w"), _ptr(rho, sh, "rho"), _ptr(p, sh, "p"), _iteration(iteration),
+            float(eps_t), int(max_iter), _ptr(gf, sh), _ptr(gr, sh), _stream(stream),
+            C.byref(inf)))
+        return gf, gr, Method3Info(inf.iterations, bool(inf.converged), inf.eps, inf.eps_start)
+
     def density_from_colour(self, phi, rho_gas, rho_liq, out=None, stream=None):
         import torch
         sh = self.shape
@@ -330,4 +370,5 @@ class Batch:
         return outs
 
 
-from .autograd import PressureSolve, pressure_solve  # noqa: E402
+from .autograd import (PressureSolve, pressure_solve, ConvergedSolve,  # noqa: E402
+                       converged_solve)

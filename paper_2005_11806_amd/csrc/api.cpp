@@ -320,6 +320,56 @@ psv_status psv_solve_adjoint(psv_plan* plan, const double* w, const double* f, c
     });
 }
 
+static void loop_info(Plan& P, hipStream_t s, bool from_init, psv_m3_info* info) {
+    if (!info) return;
+    sync_read(P, s);
+    info->iterations = P.host_flags[psv::F_STEPS];
+    info->converged = P.host_flags[psv::F_CONV];
+    info->eps = P.host_scal[psv::S_EPS];
+    info->eps_start = from_init ? NAN : P.host_scal[psv::S_EPS0];
+}
+
+// The pressure-form loop shared by Method III and the converged solve: each
+// iteration assembles q = f*scale - mean - D(rho_f^-1 G p) and omega q
+// (omega = rho, or the constant *a.rho0), tests eps_scale * sum|q| against
+// eps_t on the device before the next solve, and adds S[omega q] to p. The
+// residual of each iterate is tested before the next solve; launches after
+// convergence (or after max_iter solves) return at once. The host looks at
+// the flag every few iterations. a.f, a.rho, a.scale, a.mean and a.rho0 come
+// from the caller.
+static void residual_loop(Plan& P, bool fp32, psv::FwdArgs a, double eps_scale, double eps_t,
+                          int max_iter, const double* p_init, double* p_out, hipStream_t s) {
+    const size_t n = P.ncell();
+    bool has_p = p_init != nullptr;
+    if (has_p && p_init != p_out)
+        PSV_HIP(hipMemcpyAsync(p_out, p_init, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    const int nb = psv::fwd_x_blocks(P);
+    double* qpart = P.partials + nb;  // sum |q| per block
+    const double inv_scale = 2.0 / ((double)P.nx * P.ny);
+    const int* done = P.flags + psv::F_DONE;
+    constexpr int ITER_PER_SYNC = 4;
+    a.mode = psv::FWD_METHOD3;
+    a.partials_abs = qpart;
+    a.done = done;
+    psv::launch_m3_reset(P, s);
+    for (int launched = 0;;) {
+        for (int b = 0; b < ITER_PER_SYNC; ++b, ++launched) {
+            a.pprev = has_p ? p_out : nullptr;
+            psv::launch_fwd_x(P, fp32, a, s);
+            psv::launch_m3_check(P, qpart, nb, eps_scale, eps_t, has_p, max_iter, s);
+            psv::launch_z_solve(P, fp32, P.scal + psv::S_MEAN2, done, s);
+            psv::launch_inv_x(P, fp32, has_p ? psv::INV_ADD : psv::INV_STORE, p_out, inv_scale,
+                              done, s);
+            has_p = true;
+        }
+        sync_read(P, s);
+        if (P.host_flags[psv::F_DONE]) break;
+        if (!std::isfinite(P.host_scal[psv::S_EPS]))
+            psv::fail(PSV_ERR_NONFINITE, "iteration residual is not finite");
+        if (launched > max_iter + 1) psv::fail(PSV_ERR_HIP, "iteration loop control failed");
+    }
+}
+
 psv_status psv_solve_method3(psv_plan* plan, const double* ux, const double* uy, const double* uz,
                              const double* div_target, const double* rho, double dt, double eps_t,
                              int32_t max_iter, const double* p_init, double* p_out,
@@ -348,52 +398,96 @@ psv_status psv_solve_method3(psv_plan* plan, const double* ux, const double* uy,
             check_field(P, ux, false, "ux", s);
             check_field(P, uy, false, "uy", s);
         }
-        const size_t n = P.ncell();
         // f = (D u* - div_target) / dt, the loop-invariant part (Algorithm 1)
         double* f = P.r_ws;
         psv::launch_divergence_rhs(P, ux, uy, uz, div_target, 1.0 / dt, f, s);
-        bool has_p = p_init != nullptr;
-        if (has_p && p_init != p_out)
-            PSV_HIP(hipMemcpyAsync(p_out, p_init, n * sizeof(double), hipMemcpyDeviceToDevice, s));
-        const int nb = psv::fwd_x_blocks(P);
-        double* qpart = P.partials + nb;  // sum |f - D(rho_f^-1 G p)| per block
-        const double inv_scale = 2.0 / ((double)P.nx * P.ny);
-        const int* done = P.flags + psv::F_DONE;
-        // The residual of each iterate is tested on the device before the next
-        // solve; launches after convergence (or after max_iter solves) return at
-        // once. The host looks at the flag every few iterations.
-        constexpr int ITER_PER_SYNC = 4;
-        psv::launch_m3_reset(P, s);
-        for (int launched = 0;;) {
-            for (int b = 0; b < ITER_PER_SYNC; ++b, ++launched) {
-                psv::FwdArgs a{};
-                a.mode = psv::FWD_METHOD3;
-                a.f = f;
-                a.rho = rho;
-                a.pprev = has_p ? p_out : nullptr;
-                a.partials_abs = qpart;
-                a.done = done;
-                psv::launch_fwd_x(P, fp32, a, s);
-                psv::launch_m3_check(P, qpart, nb, dt, eps_t, has_p, max_iter, s);
-                psv::launch_z_solve(P, fp32, P.scal + psv::S_MEAN2, done, s);
-                psv::launch_inv_x(P, fp32, has_p ? psv::INV_ADD : psv::INV_STORE, p_out, inv_scale,
-                                  done, s);
-                has_p = true;
-            }
-            sync_read(P, s);
-            if (P.host_flags[psv::F_DONE]) break;
-            if (!std::isfinite(P.host_scal[psv::S_EPS]))
-                psv::fail(PSV_ERR_NONFINITE, "Method III residual is not finite");
-            if (launched > max_iter + 1) psv::fail(PSV_ERR_HIP, "Method III loop control failed");
-        }
+        psv::FwdArgs a{};
+        a.f = f;
+        a.rho = rho;
+        residual_loop(P, fp32, a, dt, eps_t, max_iter, p_init, p_out, s);
         if (want_u) psv::launch_correct_velocity(P, ux, uy, uz, p_out, rho, dt, ux_out, uy_out, uz_out, s);
-        if (info) {
-            sync_read(P, s);
-            info->iterations = P.host_flags[psv::F_STEPS];
-            info->converged = P.host_flags[psv::F_CONV];
-            info->eps = P.host_scal[psv::S_EPS];
-            info->eps_start = p_init ? NAN : P.host_scal[psv::S_EPS0];
+        loop_info(P, s, p_init != nullptr, info);
+    });
+}
+
+// Shared set-up of the converged solve and its adjoint: the mean of f*scale
+// is removed inside the loop, and the Method-I weight is min rho.
+static void converged_loop(Plan& P, const double* f, const double* scale, const double* rho,
+                           int32_t iteration, double eps_t, int32_t max_iter, const double* p_init,
+                           double* p_out, hipStream_t s) {
+    const bool fp32 = P.opts.precision == PSV_MIXED;
+    psv::FwdArgs a{};
+    a.f = f;
+    a.scale = scale;
+    a.rho = rho;
+    a.mean = P.scal + psv::S_FMEAN;
+    psv::launch_vmean(P, f, P.scal + psv::S_FMEAN, s, scale);
+    if (iteration == PSV_ITER_METHOD1) {
+        psv::launch_min_reduce(P, rho, P.scal + psv::S_RHO0, P.flags + psv::F_ARGMIN, s);
+        a.rho0 = P.scal + psv::S_RHO0;
+    }
+    residual_loop(P, fp32, a, 1.0, eps_t, max_iter, p_init, p_out, s);
+}
+
+static void need_loop_args(int32_t iteration, double eps_t, int32_t max_iter) {
+    need(iteration == PSV_ITER_METHOD1 || iteration == PSV_ITER_METHOD3,
+         "iteration must be PSV_ITER_METHOD1 or PSV_ITER_METHOD3");
+    need(std::isfinite(eps_t) && eps_t >= 0.0, "eps_t must be >= 0 and finite");
+    need(max_iter >= 1 && max_iter <= 100000, "max_iter must be in [1, 100000]");
+}
+
+psv_status psv_solve_converged(psv_plan* plan, const double* f, const double* rho,
+                               int32_t iteration, double eps_t, int32_t max_iter,
+                               const double* p_init, double* p_out, void* stream,
+                               psv_m3_info* info) {
+    return guarded([&] {
+        need(plan != nullptr, "plan is NULL");
+        need(f && rho && p_out, "f, rho and p_out must be non-NULL");
+        need(p_out != f && p_out != rho, "p_out must not alias f or rho");
+        need_loop_args(iteration, eps_t, max_iter);
+        Plan& P = plan->p;
+        hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+        PSV_HIP(hipSetDevice(P.device));
+        if (P.opts.check_inputs) {
+            check_field(P, f, false, "f", s);
+            check_field(P, rho, true, "rho", s);
+            check_field(P, p_init, false, "p_init", s);
         }
+        converged_loop(P, f, nullptr, rho, iteration, eps_t, max_iter, p_init, p_out, s);
+        loop_info(P, s, p_init != nullptr, info);
+    });
+}
+
+psv_status psv_solve_converged_adjoint(psv_plan* plan, const double* w, const double* rho,
+                                       const double* p, int32_t iteration, double eps_t,
+                                       int32_t max_iter, double* grad_f, double* grad_rho,
+                                       void* stream, psv_m3_info* info) {
+    return guarded([&] {
+        need(plan != nullptr, "plan is NULL");
+        need(w && rho, "w and rho must be non-NULL");
+        need(grad_rho == nullptr || p != nullptr, "grad_rho needs the converged pressure p");
+        for (const double* out : {static_cast<const double*>(grad_f), static_cast<const double*>(grad_rho)})
+            need(out == nullptr || (out != rho && out != p), "gradients must not alias rho or p");
+        need(grad_f == nullptr || grad_f != grad_rho, "grad_f and grad_rho must differ");
+        need_loop_args(iteration, eps_t, max_iter);
+        Plan& P = plan->p;
+        hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+        PSV_HIP(hipSetDevice(P.device));
+        if (P.opts.check_inputs) {
+            check_field(P, w, false, "w", s);
+            check_field(P, rho, true, "rho", s);
+            check_field(P, p, false, "p", s);
+        }
+        // lambda = A^+ (V^-1 w): the same converged solve on the scaled seed
+        double* lam = P.r_ws + P.ncell();
+        converged_loop(P, w, P.t.inv_vol, rho, iteration, eps_t, max_iter, nullptr, lam, s);
+        if (grad_f || grad_rho) {
+            // face products (D^T V lambda)(G p) / (2 rho_f^2) with unit weight; grad_f = V lambda
+            psv::launch_set_scalar(P.scal + psv::S_UNIT, 1.0, s);
+            psv::launch_adjoint_faces(P, lam, nullptr, rho, p ? p : lam, P.scal + psv::S_UNIT,
+                                      grad_f, grad_rho, nullptr, P.partials, s);
+        }
+        loop_info(P, s, false, info);
     });
 }
 

@@ -63,6 +63,8 @@ enum Scalar : int {
     S_MEAN2 = 6,       // mean removed by a refinement solve (discarded)
     S_EPS = 7,         // Method III: sum |f - D(rho_f^-1 G p)| of the current iterate
     S_EPS0 = 8,        // Method III: the same for p = 0 (u = u*)
+    S_FMEAN = 9,       // converged solve: volume-weighted mean of the right-hand side
+    S_UNIT = 10,       // the constant 1 (weight of the implicit adjoint's face products)
     S_NSCAL = 16
 };
 enum Flag : int { F_DONE = 0, F_ARGMIN = 1, F_STEPS = 2, F_CONV = 3, F_NFLAG = 8 };
@@ -165,10 +167,10 @@ struct FwdArgs {
     const double* rho;
     const double* pprev;  // METHOD1: previous pressure; RESID: current p
     const double* r_in;   // RESID: stored RHS
-    const double* scale;  // CONST: per-k scale or null
+    const double* scale;  // CONST, METHOD3: per-k scale of f, or null
     double* r_out;        // optional: store the assembled RHS
-    const double* rho0;   // device scalar
-    const double* mean;   // RESID: device scalar (mean removed from r)
+    const double* rho0;   // device scalar; METHOD3: constant weight instead of rho (or null)
+    const double* mean;   // RESID, METHOD3: device scalar removed from r (or f); METHOD3 may pass null
     double* partials;     // RESID: 2 per block
     double* partials_abs; // METHOD3: sum |f - D(rho_f^-1 G p)| per block
     const int* done;      // skip when *done != 0 (may be null)
@@ -223,7 +225,9 @@ void launch_adjoint_finalize(const Plan& p, int nblocks, double* grad_rho, int a
                              hipStream_t s);
 int adjoint_blocks(const Plan& p);
 void launch_scale_vol(const Plan& p, const double* x, double* out, hipStream_t s);
-void launch_vmean(const Plan& p, const double* r, double* out_scalar, hipStream_t s);
+// volume-weighted mean of r (times the per-k scale, if given)
+void launch_vmean(const Plan& p, const double* r, double* out_scalar, hipStream_t s,
+                  const double* scale = nullptr);
 void launch_fill(double* x, size_t n, double v, hipStream_t s);
 // volume-weighted mean from the forward pass's per-block sums of vol * r
 void launch_mean_finalize(const Plan& p, int nblocks, double* out_scalar, hipStream_t s);

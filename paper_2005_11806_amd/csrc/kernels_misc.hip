@@ -361,12 +361,15 @@ __global__ void k_scale_vol(Geo g, const double* __restrict__ x, double* __restr
 }
 
 // partial sums of vol[k] r[c] (volume-weighted integral)
-__global__ void __launch_bounds__(RB) k_vsum(Geo g, const double* __restrict__ r, double* partials) {
+__global__ void __launch_bounds__(RB) k_vsum(Geo g, const double* __restrict__ r,
+                                             const double* __restrict__ sc, double* partials) {
     __shared__ double sh[16];
     const unsigned plane = (unsigned)g.nx * (unsigned)g.ny, n = plane * (unsigned)g.nz;
     double acc = 0.0;
-    for (unsigned c = blockIdx.x * RB + threadIdx.x; c < n; c += gridDim.x * RB)
-        acc += g.vol[c / plane] * r[c];
+    for (unsigned c = blockIdx.x * RB + threadIdx.x; c < n; c += gridDim.x * RB) {
+        const unsigned k = c / plane;
+        acc += (sc ? g.vol[k] * sc[k] : g.vol[k]) * r[c];
+    }
     const double s = block_sum(acc, sh);
     if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
@@ -526,9 +529,10 @@ void launch_scale_vol(const Plan& p, const double* x, double* out, hipStream_t s
     PSV_HIP(hipGetLastError());
 }
 
-void launch_vmean(const Plan& p, const double* r, double* out_scalar, hipStream_t s) {
+void launch_vmean(const Plan& p, const double* r, double* out_scalar, hipStream_t s,
+                  const double* scale) {
     const int nb = grid_blocks(p.ncell(), RB);
-    hipLaunchKernelGGL(k_vsum, dim3(nb), dim3(RB), 0, s, make_geo(p), r, p.partials);
+    hipLaunchKernelGGL(k_vsum, dim3(nb), dim3(RB), 0, s, make_geo(p), r, scale, p.partials);
     hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(RB), 0, s, p.partials, nb, 1, out_scalar);
     double total = 0.0;
     for (double h : p.h) total += h;

@@ -114,8 +114,12 @@ __device__ __forceinline__ void fwd_x_tile(const XGeom& g, const Stencil& st, co
 
     const double rho0 = (MODE == FWD_METHOD1) ? *a.rho0 : 0.0;
     const double two_r0 = 2.0 * rho0;
-    const double mean = (MODE == FWD_RESID) ? *a.mean : 0.0;
-    const double sc = (MODE == FWD_CONST && a.scale) ? a.scale[k] : 1.0;
+    const double mean = (MODE == FWD_RESID || (MODE == FWD_METHOD3 && a.mean)) ? *a.mean : 0.0;
+    const double sc = ((MODE == FWD_CONST || MODE == FWD_METHOD3) && a.scale) ? a.scale[k] : 1.0;
+    // Method III weights the residual by the cell density; a constant weight
+    // (min rho) gives the Method-I iteration in the same pressure form
+    const bool const_w = MODE == FWD_METHOD3 && a.rho0 != nullptr;
+    const double omega = const_w ? *a.rho0 : 0.0;
     const double idx2 = g.inv_dx * g.inv_dx, idy2 = g.inv_dy * g.inv_dy;
     const bool has_t = k + 1 < g.nz, has_b = k > 0;
     const double igt = has_t ? st.inv_g[k + 1] : 0.0, igb = has_b ? st.inv_g[k] : 0.0;
@@ -232,10 +236,10 @@ __device__ __forceinline__ void fwd_x_tile(const XGeom& g, const Stencil& st, co
                     const double b1z = has_b ? gflux(rbz.y, rc.y, pbz.y, pc.y) * igb : 0.0;
                     d0 += (t0z - b0z) * ih;
                     d1 += (t1z - b1z) * ih;
-                    const double q0 = q.f.x - d0, q1 = q.f.y - d1;
+                    const double q0 = (q.f.x * sc - mean) - d0, q1 = (q.f.y * sc - mean) - d1;
                     qabs += fabs(q0) + fabs(q1);
-                    v0 = rc.x * q0;
-                    v1 = rc.y * q1;
+                    v0 = (const_w ? omega : rc.x) * q0;
+                    v1 = (const_w ? omega : rc.y) * q1;
                 } else {  // residual r - mean - L p
                     double l0 = ((pc.y - pc.x) - (pc.x - pw)) * idx2;
                     double l1 = ((pe - pc.y) - (pc.y - pc.x)) * idx2;

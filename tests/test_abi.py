@@ -101,6 +101,10 @@ def test_null_plan_and_pointer_errors():
         == _abi.PSV_ERR_INVALID_ARG
     assert lib.psv_density_from_colour(None, None, None, 1.0, None, None) == _abi.PSV_ERR_INVALID_ARG
     assert lib.psv_divergence(None, None, None, None, None, None) == _abi.PSV_ERR_INVALID_ARG
+    assert lib.psv_solve_converged(None, None, None, _abi.PSV_ITER_METHOD3, 0.0, 1, None, None,
+                                   None, None) == _abi.PSV_ERR_INVALID_ARG
+    assert lib.psv_solve_converged_adjoint(None, None, None, None, _abi.PSV_ITER_METHOD1, 0.0, 1,
+                                           None, None, None, None) == _abi.PSV_ERR_INVALID_ARG
     n = C.c_size_t()
     assert lib.psv_plan_workspace_size(None, C.byref(n)) == _abi.PSV_ERR_INVALID_ARG
     assert lib.psv_plan_destroy(None) == _abi.PSV_OK

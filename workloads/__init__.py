@@ -37,7 +37,8 @@ RHO_LIQUID = 1000.0
 (STREAM_FACES, STREAM_SPHERES, STREAM_TEMP, STREAM_PPREV, STREAM_W, STREAM_GRID, STREAM_FD,
  STREAM_DIVT) = range(8)
 
-CONFIG_IDS = {"const32": 0, "vd128": 1, "mixed_tanh": 2, "batch": 3, "grad256": 4, "method3": 5}
+CONFIG_IDS = {"const32": 0, "vd128": 1, "mixed_tanh": 2, "batch": 3, "grad256": 4, "method3": 5,
+              "converged": 6}
 
 BATCH_SHAPES = ((64, 64, 64), (96, 96, 128), (128, 128, 128), (128, 128, 192))
 
@@ -289,6 +290,20 @@ def method3_case(name: str, g: GridSpec, problem: int = 0, n_spheres: int = 20,
 
 def method3_128(n: int = 128) -> Method3Case:
     return method3_case("method3_128", uniform_grid(n, n, n), 0, 20)
+
+
+def converged_case(name: str, g: GridSpec, problem: int = 0, n_spheres: int = 20,
+                   rho_liq: float = 10.0) -> Case:
+    """Two-phase inputs of the converged variable-density solve and its
+    adjoint (right-hand side from the face field, seed w for the loss
+    sum(w p)), liquid density 10 as for Method III."""
+    return dataclasses.replace(
+        two_phase_case(name, g, CONFIG_IDS["converged"], problem, n_spheres, 1, with_w=True),
+        rho_liq=rho_liq)
+
+
+def converged_128(n: int = 128) -> Case:
+    return converged_case("converged_128", uniform_grid(n, n, n), 0, 20)
 
 
 def fd_directions(config: int, n_dirs: int, shape) -> np.ndarray:
