@@ -16,11 +16,29 @@ __global__ void __launch_bounds__(256) k_yz(ZArgs z, Radices rad, c2<T>* __restr
         yz_fwd_tile<T, N, KC>(z, rad, spec, tw_g, blockIdx.x, smem_raw);
 }
 
-template <typename T>
-__global__ void __launch_bounds__(IFC_SYS) k_ifc(ZArgs z, c2<T>* __restrict__ spec, const int* done) {
+template <typename T, int QM>
+__global__ void __launch_bounds__(IFC_THREADS) k_ifc(ZArgs z, c2<T>* __restrict__ spec, const int* done) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     if (done && *done) return;
-    ifc_tile<T>(z, spec, blockIdx.x, smem_raw);
+    ifc_tile<T, QM>(z, spec, blockIdx.x, smem_raw);
+}
+
+template <typename T, int QM>
+void ifc_launch(const Plan& p, const ZArgs& z, const int* done, hipStream_t s) {
+    const size_t lds = ifc_lds(p);
+    allow_lds(k_ifc<T, QM>, lds);
+    hipLaunchKernelGGL((k_ifc<T, QM>), dim3(ifc_tiles(p)), dim3(IFC_THREADS), lds, s, z,
+                       reinterpret_cast<c2<T>*>(p.spec), done);
+}
+
+template <typename T>
+void ifc_dispatch(const Plan& p, const ZArgs& z, const int* done, hipStream_t s) {
+    switch (ifc_qmax(2 * z.nc)) {
+        case 2: ifc_launch<T, 2>(p, z, done, s); break;
+        case 4: ifc_launch<T, 4>(p, z, done, s); break;
+        case 8: ifc_launch<T, 8>(p, z, done, s); break;
+        default: ifc_launch<T, 16>(p, z, done, s); break;
+    }
 }
 
 constexpr int TAB_THREADS = 64;
@@ -93,16 +111,11 @@ void launch_yz(const Plan& p, bool fp32, bool inverse, const int* done, hipStrea
 void launch_interface(const Plan& p, bool fp32, double* mean_out, const int* done, hipStream_t s) {
     check_precision(p, fp32);
     const ZArgs z = make_zargs(p, mean_out);
-    const int nblk = ifc_tiles(p);
-    const size_t lds = ifc_lds(p);
     TraceScope ts(p, fp32 ? "z_interface_fp32" : "z_interface_fp64", s);
-    if (fp32) {
-        allow_lds(k_ifc<float>, lds);
-        hipLaunchKernelGGL(k_ifc<float>, dim3(nblk), dim3(IFC_SYS), lds, s, z, (float2*)p.spec, done);
-    } else {
-        allow_lds(k_ifc<double>, lds);
-        hipLaunchKernelGGL(k_ifc<double>, dim3(nblk), dim3(IFC_SYS), lds, s, z, (double2*)p.spec, done);
-    }
+    if (fp32)
+        ifc_dispatch<float>(p, z, done, s);
+    else
+        ifc_dispatch<double>(p, z, done, s);
     PSV_HIP(hipGetLastError());
 }
 

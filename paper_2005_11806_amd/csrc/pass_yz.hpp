@@ -380,92 +380,149 @@ __device__ __forceinline__ int ifc_plane(const ZArgs& z, int r) {
     return (r >> 1) * z.kc + ((r & 1) ? z.kc - 1 : 0);
 }
 
-constexpr int IFC_SYS = 64;  // systems per interface tile (one wave)
+constexpr int IFC_THREADS = 256;  // threads per interface tile
 
-// Interface tile b: tile 0 is the (0,0) column; tile b >= 1 solves the
-// interface systems of pairs [(b-1) 64, b 64), one per lane of wave 0:
-//   d'_r = (D_r - A_r d'_{r-1}) / den_r,  x_r = d'_r - c'_r x_{r+1},
-// with A_r, c'_r and 1/den_r from the table. Rows go in segments of SEG held
-// in registers (each segment's loads issued together); d' of all but the
-// last segment waits in the spectrum for the backward sweep. A padded last
-// row (plane >= nz) is never stored.
-template <typename T>
-__device__ __forceinline__ void ifc_tile(const ZArgs& z, c2<T>* __restrict__ spec, int b,
-                                         unsigned char* smem) {
+// Lanes per interface system: up to 8 (so that a wave's access to one row
+// covers 8 consecutive pairs, whole 128-byte lines of FP64 spectrum), as few
+// as leave at most two rows per lane; more than 8 only to keep the rows per
+// lane <= 16 (R > 128, i.e. nz / kc > 64).
+__host__ __device__ inline int ifc_lanes(int R) {
+    int L = 1;
+    while (L < 8 && 2 * L < R) L *= 2;
+    while (L < 64 && 16 * L < R) L *= 2;
+    return L;
+}
+
+// One interface system on L lanes of a wave, Q <= QM consecutive rows per
+// lane (rows g Q .. g Q + Q - 1 on the lane of group g). With the plan-time
+// Thomas factors both sweeps are first-order affine recurrences,
+//   forward   d'_r = -(A_r I_r) d'_{r-1} + I_r D_r,         d'_{-1} = 0,
+//   backward  x_r  = -c'_r x_{r+1} + d'_r,                    x_R = 0, c'_{R-1} = 0,
+// so each lane composes the maps of its rows, the L lanes of a system combine
+// theirs by a log2(L)-step scan over the wave (shuffles), and every lane then
+// applies its rows from the value coming in. One load and one store per row.
+// Padding slots (j >= Q, r >= R) are identity maps in both directions; lanes
+// with no system (s = 0, the zero mode, or s >= S) carry identity maps
+// through the shuffles and store nothing.
+template <typename T, int QM>
+__device__ __forceinline__ void ifc_scan(const ZArgs& z, c2<T>* __restrict__ spec, int b) {
     using C = c2<T>;
-    constexpr int SEG = 16;
     const int S = z.mx * z.ny;
-    const size_t SP = (size_t)S;
-    if (b == 0) {
-        zero_mode_tile<T>(z, spec, SP, smem);
-        return;
-    }
-    if (threadIdx.x >= IFC_SYS) return;
-    const int s = (b - 1) * IFC_SYS + (int)threadIdx.x;
-    if (s >= S || s == 0) return;
     const int R = 2 * z.nc;
-    const int nseg = (R + SEG - 1) / SEG;
+    const int L = ifc_lanes(R);
+    const int spw = 64 / L;  // systems per wave
+    const int lane = (int)threadIdx.x & 63;
+    const int g = lane / spw;
+    const int s = (b - 1) * (IFC_THREADS / L) + ((int)threadIdx.x >> 6) * spw + (lane - g * spw);
+    const bool act = s < S && s != 0;
+    const int Q = (R + L - 1) / L;
+    const int r0 = g * Q;
     // 32-bit element offsets (every index here is below nx ny nz < 2^31)
     const T* tA = reinterpret_cast<const T*>(z.tab);
     const T* tC = tA + (size_t)R * S;
     const T* tI = tC + (size_t)R * S;
     const unsigned us = (unsigned)s, uS = (unsigned)S;
-    auto row_off = [&](int r) { return (unsigned)r * uS + us; };
-    auto plane_off = [&](int r) { return (unsigned)ifc_plane(z, r) * uS + us; };
-    C d[SEG];
-    T cp[SEG];
-    C dp{(T)0, (T)0};
-    int r0 = 0;
-    for (int sg = 0; sg < nseg; ++sg) {
-        r0 = sg * SEG;
-        const bool last = sg == nseg - 1;
-        T A[SEG], I[SEG];
+    T al[QM], cm[QM];  // forward -A_r I_r, backward -c'_r (identity 1 on padding)
+    C d[QM];           // I_r D_r, then d'_r (0 on padding)
 #pragma unroll
-        for (int j = 0; j < SEG; ++j) {
-            const int r = r0 + j;
-            A[j] = (T)0;
-            I[j] = (T)0;
-            cp[j] = (T)0;
-            d[j] = C{(T)0, (T)0};
-            if (r < R) {
-                A[j] = tA[row_off(r)];
-                I[j] = tI[row_off(r)];
-                if (last) cp[j] = tC[row_off(r)];
-                if (ifc_plane(z, r) < z.nz) d[j] = spec[plane_off(r)];
-            }
-        }
-#pragma unroll
-        for (int j = 0; j < SEG; ++j) {
-            if (r0 + j < R) {
-                dp = C{(d[j].x - A[j] * dp.x) * I[j], (d[j].y - A[j] * dp.y) * I[j]};
-                d[j] = dp;
-                if (!last) spec[plane_off(r0 + j)] = dp;
-            }
-        }
-    }
-    // backward: the last segment from registers
-    C x{(T)0, (T)0};
-#pragma unroll
-    for (int j = SEG - 1; j >= 0; --j) {
+    for (int j = 0; j < QM; ++j) {
         const int r = r0 + j;
-        if (r < R) {
-            x = r == R - 1 ? d[j] : C{d[j].x - cp[j] * x.x, d[j].y - cp[j] * x.y};
-            if (ifc_plane(z, r) < z.nz) spec[plane_off(r)] = x;
+        al[j] = (T)1;
+        cm[j] = (T)1;
+        d[j] = C{(T)0, (T)0};
+        if (act && j < Q && r < R) {
+            const unsigned o = (unsigned)r * uS + us;
+            const T I = tI[o];
+            al[j] = -tA[o] * I;
+            cm[j] = r < R - 1 ? -tC[o] : (T)0;
+            if (ifc_plane(z, r) < z.nz) {
+                const C D = spec[(unsigned)ifc_plane(z, r) * uS + us];
+                d[j] = C{I * D.x, I * D.y};
+            }
         }
     }
-    // earlier segments (all rows below R-1, so real planes) from the spectrum
-    for (int sg = nseg - 2; sg >= 0; --sg) {
-        const int q0 = sg * SEG;
+    // forward: this lane's map d'_{r0-1} -> d'_{r0+Q-1}, then an inclusive scan
+    T fa = (T)1;
+    C fb{(T)0, (T)0};
 #pragma unroll
-        for (int j = 0; j < SEG; ++j) {
-            cp[j] = tC[row_off(q0 + j)];
-            d[j] = spec[plane_off(q0 + j)];
+    for (int j = 0; j < QM; ++j) {
+        fa = al[j] * fa;
+        fb = C{al[j] * fb.x + d[j].x, al[j] * fb.y + d[j].y};
+    }
+    for (int off = 1; off < L; off *= 2) {
+        const int src = (lane - off * spw) & 63;
+        const T pa = __shfl(fa, src, 64);
+        const T px = __shfl(fb.x, src, 64), py = __shfl(fb.y, src, 64);
+        if (g >= off) {
+            fb = C{fa * px + fb.x, fa * py + fb.y};
+            fa = fa * pa;
         }
+    }
+    // d'_{r0-1} is the scanned value of the previous group (0 for g = 0)
+    const int prev = (lane - spw) & 63, next = (lane + spw) & 63;
+    C v{__shfl(fb.x, prev, 64), __shfl(fb.y, prev, 64)};
+    if (g == 0) v = C{(T)0, (T)0};
 #pragma unroll
-        for (int j = SEG - 1; j >= 0; --j) {
-            x = C{d[j].x - cp[j] * x.x, d[j].y - cp[j] * x.y};
-            spec[plane_off(q0 + j)] = x;
+    for (int j = 0; j < QM; ++j) {
+        v = C{al[j] * v.x + d[j].x, al[j] * v.y + d[j].y};
+        if (act && j < Q && r0 + j < R) d[j] = v;
+    }
+    // backward: this lane's map x_{r0+Q} -> x_{r0}, then a suffix scan
+    T ba = (T)1;
+    C bb{(T)0, (T)0};
+#pragma unroll
+    for (int j = QM - 1; j >= 0; --j) {
+        ba = cm[j] * ba;
+        bb = C{cm[j] * bb.x + d[j].x, cm[j] * bb.y + d[j].y};
+    }
+    for (int off = 1; off < L; off *= 2) {
+        const int src = (lane + off * spw) & 63;
+        const T pa = __shfl(ba, src, 64);
+        const T px = __shfl(bb.x, src, 64), py = __shfl(bb.y, src, 64);
+        if (g + off < L) {
+            bb = C{ba * px + bb.x, ba * py + bb.y};
+            ba = ba * pa;
         }
+    }
+    C x{__shfl(bb.x, next, 64), __shfl(bb.y, next, 64)};
+    if (g == L - 1) x = C{(T)0, (T)0};
+#pragma unroll
+    for (int j = QM - 1; j >= 0; --j) {
+        x = C{cm[j] * x.x + d[j].x, cm[j] * x.y + d[j].y};
+        const int r = r0 + j;
+        if (act && j < Q && r < R && ifc_plane(z, r) < z.nz)
+            spec[(unsigned)ifc_plane(z, r) * uS + us] = x;
+    }
+}
+
+// Register rows per lane for R interface rows: 2, 4, 8 or 16 (nz / kc <= 512).
+__host__ __device__ inline int ifc_qmax(int R) {
+    const int q = (R + ifc_lanes(R) - 1) / ifc_lanes(R);
+    return q <= 2 ? 2 : (q <= 4 ? 4 : (q <= 8 ? 8 : 16));
+}
+
+// Interface tile b: tile 0 is the (0,0) column; tile b >= 1 solves the
+// interface systems of pairs [(b-1) P, b P), P = IFC_THREADS / L. Needs
+// blockDim.x == IFC_THREADS and QM == ifc_qmax(2 nc) (QM = 0: chosen here).
+template <typename T, int QM = 0>
+__device__ __forceinline__ void ifc_tile(const ZArgs& z, c2<T>* __restrict__ spec, int b,
+                                         unsigned char* smem) {
+    if (b == 0) {
+        zero_mode_tile<T>(z, spec, (size_t)z.mx * z.ny, smem);
+        return;
+    }
+    if constexpr (QM > 0) {
+        ifc_scan<T, QM>(z, spec, b);
+    } else {
+        const int q = ifc_qmax(2 * z.nc);
+        if (q == 2)
+            ifc_scan<T, 2>(z, spec, b);
+        else if (q == 4)
+            ifc_scan<T, 4>(z, spec, b);
+        else if (q == 8)
+            ifc_scan<T, 8>(z, spec, b);
+        else
+            ifc_scan<T, 16>(z, spec, b);
     }
 }
 
@@ -546,7 +603,10 @@ inline ZArgs make_zargs(const Plan& p, double* mean_out) {
 }
 
 inline int yz_tiles(const Plan& p) { return p.mx * ((p.nz + p.lp.kc - 1) / p.lp.kc); }
-inline int ifc_tiles(const Plan& p) { return 1 + (p.mx * p.ny + IFC_SYS - 1) / IFC_SYS; }
+inline int ifc_tiles(const Plan& p) {
+    const int per = IFC_THREADS / ifc_lanes(2 * ((p.nz + p.lp.kc - 1) / p.lp.kc));
+    return 1 + (p.mx * p.ny + per - 1) / per;
+}
 inline size_t ifc_lds(const Plan& p) { return zero_mode_lds(p.nz); }
 
 }  // namespace psv

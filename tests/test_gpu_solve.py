@@ -150,6 +150,28 @@ def test_chunk_rows_fp64(gpu, kc, shape, stretched):
     assert info.relres <= 1e-12
 
 
+# The interface systems (2 ceil(nz/kc) rows per pair) are spread over up to 64
+# lanes with 2, 4 or 16 register rows each; long columns reach every layout
+# (rows 38, 200, 516, 512 and 1024).
+@pytest.mark.parametrize("shape,kc,stretched", [((8, 8, 300), 16, True), ((8, 8, 400), 4, False),
+                                                ((8, 6, 1030), 4, True), ((8, 4, 2048), 8, False),
+                                                ((4, 4, 2048), 4, True)])
+def test_interface_lane_layouts(gpu, shape, kc, stretched):
+    nx, ny, nz = shape
+    lz = nz / 64.0
+    spec = W.GridSpec(nx, ny, nz, 1.0, 0.9, lz, W.tanh_faces(nz, lz, 1.5) if stretched else None)
+    case = W.two_phase_case("lanes", spec, 1, 13, n_spheres=3)
+    g, f, rho, pp = oracle_inputs(case)
+    say(f"interface lanes {shape} kc={kc} stretched={stretched}")
+    plan = gpu.Plan(gpu.Grid.from_spec(spec), chunk_rows=kc)
+    ps, _ = O.solve(f, g, rho, pp, n_steps=2)
+    p, info = plan.solve(dev(f), rho=dev(rho), p_prev=dev(pp), n_steps=2, info=True)
+    err = rel_max_err(host(p), ps[1])
+    say(f"  err {err:.3e} relres {info.relres:.3e}")
+    assert err <= TOL_FP64
+    assert info.relres <= 1e-12
+
+
 @pytest.mark.parametrize("kc", [4, 8, 16])
 def test_chunk_rows_mixed(gpu, kc):
     spec = W.GridSpec(48, 32, 37, 1.0, 1.0, 1.5, W.tanh_faces(37, 1.5, 1.5))
