@@ -20,8 +20,9 @@
  *
  * Conventions for every call:
  *  - Field pointers are DEVICE pointers to contiguous float64 arrays in
- *    C order [nz][ny][nx] (x fastest), owned by the caller; the library
- *    never frees or retains them beyond the call's stream work.
+ *    C order [nz][ny][nx] (x fastest), 16-byte aligned (the passes move
+ *    pairs of doubles; PSV_ERR_INVALID_ARG otherwise), owned by the caller;
+ *    the library never frees or retains them beyond the call's stream work.
  *  - `stream` is a hipStream_t (NULL = the default stream). Work is enqueued
  *    asynchronously; a call returns before the GPU finishes unless it
  *    documents a synchronisation.

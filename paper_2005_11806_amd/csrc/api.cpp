@@ -3,7 +3,9 @@
 // eigenexpansion solve on the caller's stream. Exceptions never cross the ABI.
 #include <algorithm>
 #include <cmath>
+#include <cstdint>
 #include <cstring>
+#include <initializer_list>
 #include <string>
 
 #include "internal.hpp"
@@ -57,6 +59,13 @@ psv_status guarded(F&& fn) {
 
 void need(bool cond, const char* msg) {
     if (!cond) psv::fail(PSV_ERR_INVALID_ARG, msg);
+}
+
+// The passes read and write fields as pairs of doubles (16-byte accesses).
+void need_aligned(std::initializer_list<const void*> ptrs) {
+    for (const void* q : ptrs)
+        need((reinterpret_cast<uintptr_t>(q) & 15) == 0,
+             "field pointers must be 16-byte aligned");
 }
 
 using psv::Plan;
@@ -216,6 +225,7 @@ psv_status psv_solve(psv_plan* plan, const double* f, const double* rho, double 
         need(p_out != nullptr, "p_out is NULL");
         need(n_steps >= 1, "n_steps must be >= 1");
         need(std::isfinite(rho0), "rho0 must be finite");
+        need_aligned({f, rho, p_prev, p_out});
         Plan& P = plan->p;
         const bool method1 = P.opts.method == PSV_SPLIT_RHO0;
         if (method1)
@@ -287,6 +297,7 @@ psv_status psv_solve_adjoint(psv_plan* plan, const double* w, const double* f, c
         need(plan != nullptr, "plan is NULL");
         need(w != nullptr, "w is NULL");
         need(std::isfinite(rho0), "rho0 must be finite");
+        need_aligned({w, f, rho, p_prev, grad_f, grad_rho, grad_p_prev});
         Plan& P = plan->p;
         const bool method1 = P.opts.method == PSV_SPLIT_RHO0;
         hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -384,6 +395,7 @@ psv_status psv_solve_method3(psv_plan* plan, const double* ux, const double* uy,
         need(std::isfinite(dt) && dt > 0.0, "dt must be positive and finite");
         need(std::isfinite(eps_t) && eps_t >= 0.0, "eps_t must be >= 0 and finite");
         need(max_iter >= 1 && max_iter <= 100000, "max_iter must be in [1, 100000]");
+        need_aligned({ux, uy, uz, div_target, rho, p_init, p_out, ux_out, uy_out, uz_out});
         const bool want_u = ux_out && uy_out && uz_out;
         need(want_u || (!ux_out && !uy_out && !uz_out), "give all three velocity outputs or none");
         if (want_u)
@@ -444,6 +456,7 @@ psv_status psv_solve_converged(psv_plan* plan, const double* f, const double* rh
         need(plan != nullptr, "plan is NULL");
         need(f && rho && p_out, "f, rho and p_out must be non-NULL");
         need(p_out != f && p_out != rho, "p_out must not alias f or rho");
+        need_aligned({f, rho, p_init, p_out});
         need_loop_args(iteration, eps_t, max_iter);
         Plan& P = plan->p;
         hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -469,6 +482,7 @@ psv_status psv_solve_converged_adjoint(psv_plan* plan, const double* w, const do
         for (const double* out : {static_cast<const double*>(grad_f), static_cast<const double*>(grad_rho)})
             need(out == nullptr || (out != rho && out != p), "gradients must not alias rho or p");
         need(grad_f == nullptr || grad_f != grad_rho, "grad_f and grad_rho must differ");
+        need_aligned({w, rho, p, grad_f, grad_rho});
         need_loop_args(iteration, eps_t, max_iter);
         Plan& P = plan->p;
         hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -496,6 +510,7 @@ psv_status psv_density_from_colour(const psv_plan* plan, const double* phi, cons
     return guarded([&] {
         need(plan && phi && rho_gas && rho_out, "plan, phi, rho_gas and rho_out must be non-NULL");
         need(std::isfinite(rho_liq) && rho_liq > 0.0, "rho_liq must be positive and finite");
+        need_aligned({phi, rho_gas, rho_out});
         PSV_HIP(hipSetDevice(plan->p.device));
         psv::launch_density(plan->p, phi, rho_gas, rho_liq, rho_out, reinterpret_cast<hipStream_t>(stream));
     });
@@ -505,6 +520,7 @@ psv_status psv_divergence(const psv_plan* plan, const double* ux, const double* 
                           const double* uz, double* div_out, void* stream) {
     return guarded([&] {
         need(plan && ux && uy && uz && div_out, "all pointers must be non-NULL");
+        need_aligned({ux, uy, uz, div_out});
         PSV_HIP(hipSetDevice(plan->p.device));
         psv::launch_divergence(plan->p, ux, uy, uz, div_out, reinterpret_cast<hipStream_t>(stream));
     });
@@ -514,6 +530,7 @@ psv_status psv_relres(psv_plan* plan, const double* r, const double* p, void* st
                       double* relres) {
     return guarded([&] {
         need(plan && r && p && relres, "all pointers must be non-NULL");
+        need_aligned({r, p});
         Plan& P = plan->p;
         hipStream_t s = reinterpret_cast<hipStream_t>(stream);
         PSV_HIP(hipSetDevice(P.device));
@@ -562,6 +579,7 @@ psv_status psv_batch_solve(psv_batch* batch, const double* const* f, const doubl
         const bool fp32 = psv::batch_fp32(*batch);
         for (int p = 0; p < n; ++p) {
             need(f[p] != nullptr && p_out[p] != nullptr, "f[p] and p_out[p] must be non-NULL");
+            need_aligned({f[p], p_out[p], rho ? rho[p] : nullptr, p_prev ? p_prev[p] : nullptr});
             if (method1) {
                 need(rho != nullptr && rho[p] != nullptr, "rho[p] is required by Method I");
                 need(p_prev != nullptr && p_prev[p] != nullptr, "p_prev[p] is required by Method I");

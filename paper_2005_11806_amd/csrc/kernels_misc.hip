@@ -302,53 +302,122 @@ struct AdjArgs {
     double* partials;
 };
 
+// One face between cells L and R of the adjoint's face products:
+// t = (D^T mu)_F = mu_L ih_L - mu_R ih_R (ih the widths normal to F), g = (G p)_F,
+// 1/rho_f = 2 / (rho_L + rho_R). Adds t g rho0 / (2 rho_f^2) to the grad_rho of
+// both cells (gr_l, gr_r), the face's share of G^T((1 - rho0/rho_f) t) to their
+// grad_p (gp_l, gp_r), and returns -t g / rho_f (the face's part of d/drho0).
+struct FaceOut {
+    double gr, gp_l, gp_r, r0;
+};
+__device__ __forceinline__ FaceOut adj_face(double mul, double ihl, double mur, double ihr,
+                                            double rl, double rr, double pl, double pr,
+                                            double inv_d, double rho0) {
+    const double t = mul * ihl - mur * ihr;
+    const double irf = 2.0 * rcp_nr(rl + rr);
+    const double gf = t * ((pr - pl) * inv_d);
+    const double bdt = (1.0 - rho0 * irf) * t * inv_d;
+    return FaceOut{0.5 * gf * rho0 * irf * irf, -bdt, bdt, -gf * irf};
+}
+
+// Face products of the adjoint, one thread per pair of cells (2n, 2n+1) of an
+// x line: 16-byte loads of x, rho and p on the pair and on its y and z
+// neighbour pairs, single loads for the two x neighbours outside the pair.
+// The pair's three x faces (west, middle, east), four y faces and up to four z
+// faces are evaluated once each; each cell sums the faces it touches. The
+// d/drho0 partial counts each face once, at the cell on its lower (west,
+// south or bottom) side. nx is even, so pairs never straddle lines.
 __global__ void __launch_bounds__(RB) k_adjoint_faces(Geo g, AdjArgs a) {
     __shared__ double sh[16];
     const unsigned nx = (unsigned)g.nx, ny = (unsigned)g.ny, nz = (unsigned)g.nz;
-    const unsigned plane = nx * ny, n = plane * nz;  // every index is below 2^31
+    const unsigned M = nx / 2;
+    const unsigned plane2 = M * ny, npair = plane2 * nz;  // every index is below 2^31
     const double rho0 = *a.rho0p;
+    const double2* X = reinterpret_cast<const double2*>(a.x);
+    const double2* RH = reinterpret_cast<const double2*>(a.rho);
+    const double2* P = reinterpret_cast<const double2*>(a.pp);
     double acc = 0.0;
-    for (unsigned c = blockIdx.x * RB + threadIdx.x; c < n; c += gridDim.x * RB) {
-        unsigned i, j, k;
-        cell_ijk(c, g, i, j, k);
-        const double lc = g.vol[k] * a.x[c], rc = a.rho[c], pc = a.pp[c];
-        const double ihc = g.inv_h[k];
-        double gr = 0.0, gp = 0.0;
-        // neighbour offsets: east, west, north, south, top, bottom
-        unsigned nb[6];
-        bool has[6] = {true, true, true, true, k + 1 < nz, k > 0};
-        nb[0] = i + 1 == nx ? c + 1 - nx : c + 1;
-        nb[1] = i == 0 ? c + nx - 1 : c - 1;
-        nb[2] = j + 1 == ny ? c + nx - plane : c + nx;
-        nb[3] = j == 0 ? c + plane - nx : c - nx;
-        nb[4] = has[4] ? c + plane : c;
-        nb[5] = has[5] ? c - plane : c;
-#pragma unroll
-        for (int q = 0; q < 6; ++q) {
-            if (!has[q]) continue;
-            const unsigned o = nb[q];
-            const unsigned ko = (q == 4) ? k + 1 : (q == 5 ? k - 1 : k);
-            const double lo = g.vol[ko] * a.x[o], ro = a.rho[o], po = a.pp[o];
-            // plus faces (q even): c is the left cell; minus faces: c is the right cell
-            const bool plus = (q & 1) == 0;
-            double ihc_o, inv_d;
-            if (q < 2) { ihc_o = g.inv_dx; inv_d = g.inv_dx; }
-            else if (q < 4) { ihc_o = g.inv_dy; inv_d = g.inv_dy; }
-            else { ihc_o = g.inv_h[q == 4 ? k + 1 : k - 1]; inv_d = g.inv_g[q == 4 ? k + 1 : k]; }
-            const double ihl = (q < 4) ? ihc_o : ihc;  // own width in this direction
-            const double dt = plus ? (lc * ihl - lo * ihc_o) : (lo * ihc_o - lc * ihl);
-            const double gpf = plus ? (po - pc) * inv_d : (pc - po) * inv_d;
-            const double irf = 2.0 * rcp_nr(rc + ro);  // 1 / rho_f
-            const double gf = dt * gpf;
-            gr += 0.5 * gf * rho0 * irf * irf;
-            const double bdt = (1.0 - rho0 * irf) * dt;
-            gp += plus ? -bdt * inv_d : bdt * inv_d;
-            if (plus) acc -= gf * irf;
+    for (unsigned q = blockIdx.x * RB + threadIdx.x; q < npair; q += gridDim.x * RB) {
+        const unsigned line = q / M;
+        const unsigned n = q - line * M;
+        const unsigned k = line / ny, j = line - k * ny;
+        const double vk = g.vol[k], ihk = g.inv_h[k];
+        const double idx = g.inv_dx, idy = g.inv_dy;
+        const double2 xc = X[q], rc = RH[q], pc = P[q];
+        const double m0 = vk * xc.x, m1 = vk * xc.y;
+        // x neighbours outside the pair (periodic within the line)
+        const unsigned cw = line * nx + (n == 0 ? nx - 1 : 2 * n - 1);
+        const unsigned ce = line * nx + (n + 1 == M ? 0 : 2 * n + 2);
+        const double mw = vk * a.x[cw], rw = a.rho[cw], pw = a.pp[cw];
+        const double me = vk * a.x[ce], re = a.rho[ce], pe = a.pp[ce];
+        double gr0 = 0.0, gr1 = 0.0, gp0 = 0.0, gp1 = 0.0;
+        // x faces: west of 2n (lower cell outside), middle, east of 2n+1
+        FaceOut f = adj_face(mw, idx, m0, idx, rw, rc.x, pw, pc.x, idx, rho0);
+        gr0 += f.gr;
+        gp0 += f.gp_r;
+        f = adj_face(m0, idx, m1, idx, rc.x, rc.y, pc.x, pc.y, idx, rho0);
+        gr0 += f.gr;
+        gr1 += f.gr;
+        gp0 += f.gp_l;
+        gp1 += f.gp_r;
+        acc += f.r0;
+        f = adj_face(m1, idx, me, idx, rc.y, re, pc.y, pe, idx, rho0);
+        gr1 += f.gr;
+        gp1 += f.gp_l;
+        acc += f.r0;
+        // y faces: north (this pair lower) and south (periodic)
+        {
+            const unsigned qn = (j + 1 == ny) ? q + M - plane2 : q + M;
+            const unsigned qs = (j == 0) ? q + plane2 - M : q - M;
+            const double2 xn = X[qn], rn = RH[qn], pn = P[qn];
+            const double2 xs = X[qs], rs = RH[qs], ps = P[qs];
+            f = adj_face(m0, idy, vk * xn.x, idy, rc.x, rn.x, pc.x, pn.x, idy, rho0);
+            gr0 += f.gr;
+            gp0 += f.gp_l;
+            acc += f.r0;
+            f = adj_face(m1, idy, vk * xn.y, idy, rc.y, rn.y, pc.y, pn.y, idy, rho0);
+            gr1 += f.gr;
+            gp1 += f.gp_l;
+            acc += f.r0;
+            f = adj_face(vk * xs.x, idy, m0, idy, rs.x, rc.x, ps.x, pc.x, idy, rho0);
+            gr0 += f.gr;
+            gp0 += f.gp_r;
+            f = adj_face(vk * xs.y, idy, m1, idy, rs.y, rc.y, ps.y, pc.y, idy, rho0);
+            gr1 += f.gr;
+            gp1 += f.gp_r;
         }
-        acc += lc * (a.f ? a.f[c] : 0.0);
-        if (a.grad_f) a.grad_f[c] = rho0 * lc;
-        if (a.grad_rho) a.grad_rho[c] = gr;
-        if (a.grad_p) a.grad_p[c] = gp;
+        // z faces: top (this pair lower) and bottom; none at the walls
+        if (k + 1 < nz) {
+            const unsigned qt = q + plane2;
+            const double2 xt = X[qt], rt = RH[qt], pt = P[qt];
+            const double vt = g.vol[k + 1], iht = g.inv_h[k + 1], igt = g.inv_g[k + 1];
+            f = adj_face(m0, ihk, vt * xt.x, iht, rc.x, rt.x, pc.x, pt.x, igt, rho0);
+            gr0 += f.gr;
+            gp0 += f.gp_l;
+            acc += f.r0;
+            f = adj_face(m1, ihk, vt * xt.y, iht, rc.y, rt.y, pc.y, pt.y, igt, rho0);
+            gr1 += f.gr;
+            gp1 += f.gp_l;
+            acc += f.r0;
+        }
+        if (k > 0) {
+            const unsigned qb = q - plane2;
+            const double2 xb = X[qb], rb = RH[qb], pb = P[qb];
+            const double vb = g.vol[k - 1], ihb = g.inv_h[k - 1], igb = g.inv_g[k];
+            f = adj_face(vb * xb.x, ihb, m0, ihk, rb.x, rc.x, pb.x, pc.x, igb, rho0);
+            gr0 += f.gr;
+            gp0 += f.gp_r;
+            f = adj_face(vb * xb.y, ihb, m1, ihk, rb.y, rc.y, pb.y, pc.y, igb, rho0);
+            gr1 += f.gr;
+            gp1 += f.gp_r;
+        }
+        if (a.f) {
+            const double2 fc = reinterpret_cast<const double2*>(a.f)[q];
+            acc += m0 * fc.x + m1 * fc.y;
+        }
+        if (a.grad_f) reinterpret_cast<double2*>(a.grad_f)[q] = double2{rho0 * m0, rho0 * m1};
+        if (a.grad_rho) reinterpret_cast<double2*>(a.grad_rho)[q] = double2{gr0, gr1};
+        if (a.grad_p) reinterpret_cast<double2*>(a.grad_p)[q] = double2{gp0, gp1};
     }
     const double s = block_sum(acc, sh);
     if (threadIdx.x == 0) a.partials[blockIdx.x] = s;
@@ -421,7 +490,7 @@ int grid_blocks(size_t n, int thr) {
 }  // namespace
 
 // up to 4096 blocks (the plan's partials hold at least 8192 values)
-int adjoint_blocks(const Plan& p) { return (int)std::min<size_t>(4096, (p.ncell() + RB - 1) / RB); }
+int adjoint_blocks(const Plan& p) { return (int)std::min<size_t>(4096, (p.ncell() / 2 + RB - 1) / RB); }
 
 void launch_min_reduce(const Plan& p, const double* x, double* out_scalar, int* argmin_out,
                        hipStream_t s) {

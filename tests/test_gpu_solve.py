@@ -219,3 +219,24 @@ def test_input_checks(gpu):
         plan.solve(dev(f), rho=dev(rho), rho0=2.0)
     assert e.value.status == psv._abi.PSV_ERR_INVALID_ARG
     plan.solve(dev(f), rho=dev(rho))  # valid inputs still pass
+
+
+def test_misaligned_field_pointers_rejected(gpu):
+    """Contiguous views at an 8-byte offset are refused before any launch."""
+    import torch
+    import paper_2005_11806_amd as psv
+    spec = W.uniform_grid(8, 8, 8)
+    plan = gpu.Plan(gpu.Grid.from_spec(spec))
+    base = torch.zeros(8 * 64 + 1, dtype=torch.float64, device="cuda")
+    odd = base[1:].view(8, 8, 8)
+    rho = dev(np.ones((8, 8, 8)))
+    for call in (lambda: plan.solve(odd, rho=rho),
+                 lambda: plan.solve(rho, rho=odd),
+                 lambda: plan.solve(rho, rho=rho, out=odd),
+                 lambda: plan.adjoint(odd, rho=rho, p_prev=rho),
+                 lambda: plan.solve_converged(odd, rho, max_iter=1)):
+        with pytest.raises(psv.PsvError) as e:
+            call()
+        assert e.value.status == psv._abi.PSV_ERR_INVALID_ARG
+    p = plan.solve(rho, rho=rho)  # aligned inputs still pass
+    assert np.isfinite(host(p)).all()
