@@ -191,10 +191,16 @@ __host__ __device__ constexpr int radix_prefix(RadixList L, int s) {
 // (the radix-R scatter of a Stockham stage then spreads over the banks
 // instead of hitting the same ones); element i lives at at(i).
 struct NoPad {
-    __device__ static constexpr int at(int i) { return i; }
+    __host__ __device__ static constexpr int at(int i) { return i; }
+    __host__ __device__ static constexpr bool linear(int) { return true; }
+    __host__ __device__ static constexpr int step(int s) { return s; }
 };
 struct Pad8 {
-    __device__ static constexpr int at(int i) { return i + (i >> 3); }
+    __host__ __device__ static constexpr int at(int i) { return i + (i >> 3); }
+    // at(i + k s) = at(i) + k step(s) whenever s is a multiple of 8, so the
+    // addresses of a butterfly are one base plus constant offsets
+    __host__ __device__ static constexpr bool linear(int s) { return s % 8 == 0; }
+    __host__ __device__ static constexpr int step(int s) { return s + s / 8; }
 };
 
 // Butterfly j of a radix-R Stockham stage (NS = product of the earlier
@@ -203,8 +209,14 @@ struct Pad8 {
 template <int R, int DIR, int NS, int NB, int TSTEP, typename P = NoPad, typename C>
 __device__ __forceinline__ void stockham_load_ct(const C* __restrict__ in, int j,
                                                  const C* __restrict__ tw, C* v, int off = 0) {
+    if constexpr (P::linear(NB)) {
+        const int b = P::at(off + j);
 #pragma unroll
-    for (int r = 0; r < R; ++r) v[r] = in[P::at(off + j + r * NB)];
+        for (int r = 0; r < R; ++r) v[r] = in[b + r * P::step(NB)];
+    } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[r] = in[P::at(off + j + r * NB)];
+    }
     const int k = j % NS;
     if (NS > 1) {
 #pragma unroll
@@ -220,23 +232,32 @@ __device__ __forceinline__ void stockham_load_ct(const C* __restrict__ in, int j
     if (R == 8) bfly8<DIR>(v);
 }
 
-template <int R, int NS, typename P = NoPad, typename C>
+// A8: off is a multiple of 8 (lines of a length divisible by 8), so in a
+// first stage (NS = 1) with R dividing 8 the R outputs of a butterfly stay in
+// one group of 8 elements.
+template <int R, int NS, typename P = NoPad, bool A8 = false, typename C>
 __device__ __forceinline__ void stockham_store_ct(C* __restrict__ out, int j, const C* v,
                                                   int off = 0) {
     const int base = off + (j / NS) * NS * R + j % NS;
+    if constexpr (P::linear(NS)) {
+        const int b = P::at(base);
 #pragma unroll
-    for (int r = 0; r < R; ++r) out[P::at(base + r * NS)] = v[r];
+        for (int r = 0; r < R; ++r) out[b + r * P::step(NS)] = v[r];
+    } else if constexpr (A8 && NS == 1 && 8 % R == 0) {
+        const int b = P::at(base);
+#pragma unroll
+        for (int r = 0; r < R; ++r) out[b + r] = v[r];
+    } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) out[P::at(base + r * NS)] = v[r];
+    }
 }
 
-template <int R, int DIR, int NS, int NB, int TSTEP, typename C>
-__device__ __forceinline__ void stockham_bfly_ct(const C* __restrict__ in, C* __restrict__ out,
-                                                 int j, const C* __restrict__ tw) {
-    C v[R];
-    stockham_load_ct<R, DIR, NS, NB, TSTEP>(in, j, tw, v);
-    stockham_store_ct<R, NS>(out, j, v);
-}
-
-template <int N, int S, int DIR, int TWM, typename C>
+// Two-buffer variant: stage S reads src and writes dst (both in layout P,
+// line l starting at element l * lstride, lstride a multiple of 8 when N is),
+// then the buffers swap. Returns the buffer holding the result; ends with the
+// block synchronised.
+template <int N, int S, int DIR, int TWM, typename P = NoPad, typename C>
 __device__ __forceinline__ C* fft_stages(C* src, C* dst, int nlines, int lstride,
                                          const C* __restrict__ tw) {
     constexpr RadixList RL = radix_list(N);
@@ -251,10 +272,12 @@ __device__ __forceinline__ C* fft_stages(C* src, C* dst, int nlines, int lstride
         for (int t = threadIdx.x; t < total; t += 256) {
             const int line = t / NB;
             const int j = t - line * NB;
-            stockham_bfly_ct<R, DIR, NS, NB, TSTEP>(src + line * lstride, dst + line * lstride, j, tw);
+            C v[R];
+            stockham_load_ct<R, DIR, NS, NB, TSTEP, P>(src, j, tw, v, line * lstride);
+            stockham_store_ct<R, NS, P, N % 8 == 0>(dst, j, v, line * lstride);
         }
         __syncthreads();
-        return fft_stages<N, S + 1, DIR, TWM>(dst, src, nlines, lstride, tw);
+        return fft_stages<N, S + 1, DIR, TWM, P>(dst, src, nlines, lstride, tw);
     }
 }
 
@@ -287,7 +310,7 @@ __device__ __forceinline__ void fft_inplace(C* buf, const C* __restrict__ tw) {
             const int t = (int)threadIdx.x + it * 256;
             if (TOTAL % 256 == 0 || t < TOTAL) {
                 const int line = t / NB;
-                stockham_store_ct<R, NS, P>(buf, t - line * NB, v[it], line * N);
+                stockham_store_ct<R, NS, P, N % 8 == 0>(buf, t - line * NB, v[it], line * N);
             }
         }
         __syncthreads();
@@ -302,12 +325,13 @@ __device__ __forceinline__ double rcp_nr(double s) {
     return fma(r, fma(-s, r, 1.0), r);
 }
 
-// N = 0 selects the runtime-length routine above.
-template <int N, int DIR, int TWM, typename C>
+// N = 0 selects the runtime-length routine above (layout P applies to N > 0
+// only; the runtime routine reads and writes unpadded lines).
+template <int N, int DIR, int TWM, typename P = NoPad, typename C>
 __device__ __forceinline__ C* lds_fft_n(C* buf0, C* buf1, int L, int nlines, int lstride,
                                         const Radices& rp, const C* __restrict__ tw) {
     if constexpr (N > 0) {
-        return fft_stages<N, 0, DIR, TWM>(buf0, buf1, nlines, lstride, tw);
+        return fft_stages<N, 0, DIR, TWM, P>(buf0, buf1, nlines, lstride, tw);
     } else {
         return lds_fft<DIR>(buf0, buf1, L, nlines, lstride, rp, tw, L * TWM);
     }

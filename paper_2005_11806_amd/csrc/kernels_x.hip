@@ -34,8 +34,10 @@ __global__ void __launch_bounds__(256) k_inv_x(XGeom g, const c2<TC>* __restrict
 template <typename TC, typename TS, int MODE, int N>
 void fwd_launch(const Plan& p, const XGeom& g, const Stencil& st, const FwdArgs& a,
                 const c2<TC>* tw, hipStream_t s) {
-    hipLaunchKernelGGL((k_fwd_x<TC, TS, MODE, N>), dim3(g.tiles * p.nz), dim3(256),
-                       fwd_x_lds(g, sizeof(c2<TC>)), s, g, st, a, tw,
+    const size_t lds = fwd_x_lds(g, sizeof(c2<TC>));
+    allow_lds(k_fwd_x<TC, TS, MODE, N>, lds);
+    hipLaunchKernelGGL((k_fwd_x<TC, TS, MODE, N>), dim3(g.tiles * p.nz), dim3(256), lds, s, g,
+                       st, a, tw,
                        reinterpret_cast<c2<TS>*>(p.spec));
 }
 
@@ -61,8 +63,9 @@ void fwd_impl(const Plan& p, const FwdArgs& a, hipStream_t s) {
 template <typename TC, typename TS, int MODE, int N>
 void inv_launch(const Plan& p, const XGeom& g, const c2<TC>* tw, double* out, double scale,
                 const int* done, hipStream_t s) {
-    hipLaunchKernelGGL((k_inv_x<TC, TS, MODE, N>), dim3(g.tiles * p.nz), dim3(256),
-                       inv_x_lds(g, sizeof(c2<TC>)), s, g, tw,
+    const size_t lds = inv_x_lds(g, sizeof(c2<TC>));
+    allow_lds(k_inv_x<TC, TS, MODE, N>, lds);
+    hipLaunchKernelGGL((k_inv_x<TC, TS, MODE, N>), dim3(g.tiles * p.nz), dim3(256), lds, s, g, tw,
                        reinterpret_cast<const c2<TS>*>(p.spec), out, p.t.vol, scale, done);
 }
 

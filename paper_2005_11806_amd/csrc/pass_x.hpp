@@ -9,6 +9,8 @@
 // block has 256 threads.
 #pragma once
 
+#include <type_traits>
+
 #include "internal.hpp"
 
 namespace psv {
@@ -25,18 +27,32 @@ struct Stencil {
     const double* vol;
 };
 
+// FFT buffers of the x tiles hold lb lines of M elements in the layout
+// XLayout<N>: one pad element after every 8 for the compile-time lengths (the
+// radix scatter of a Stockham stage then spreads over the LDS banks), plain
+// for runtime lengths. Either way a buffer spans xbuf_span(lb M) elements.
+template <int N>
+using XLayout = std::conditional_t<(N > 0), Pad8, NoPad>;
+__host__ __device__ inline int xbuf_span(int n) { return n + (n >> 3) + 1; }
+
 // LDS bytes of the x tiles for complex element size csz. Forward: FFT buffer,
 // twiddles, then either the second FFT buffer or the staged rows of p and rho
 // (lb + 2 rows each, FP64), which the second buffer reuses after assembly.
+// Inverse: FFT buffer, the staged half spectrum (lb x (M+1), reused as the
+// second FFT buffer), twiddles.
 inline size_t fwd_x_lds_n(int nx, int lb, size_t csz) {
     const size_t M = nx / 2;
     const size_t stage = (size_t)2 * (lb + 2) * nx * sizeof(double);
-    const size_t buf = (size_t)lb * M * csz;
+    const size_t buf = (size_t)xbuf_span(lb * (int)M) * csz;
     return buf + 2 * M * csz + 16 + (stage > buf ? stage : buf);
 }
+__host__ __device__ inline int inv_x_stage_span(int M, int lb) {
+    const int a = lb * (M + 1), b = xbuf_span(lb * M);
+    return a > b ? a : b;
+}
 inline size_t inv_x_lds_n(int nx, int lb, size_t csz) {
-    const size_t M = nx / 2;
-    return ((size_t)lb * (2 * M + 1) + 2 * M) * csz;
+    const int M = nx / 2;
+    return ((size_t)xbuf_span(lb * M) + inv_x_stage_span(M, lb) + 2 * (size_t)M) * csz;
 }
 inline size_t fwd_x_lds(const XGeom& g, size_t csz) { return fwd_x_lds_n(g.nx, g.lb, csz); }
 inline size_t inv_x_lds(const XGeom& g, size_t csz) { return inv_x_lds_n(g.nx, g.lb, csz); }
@@ -101,8 +117,9 @@ __device__ __forceinline__ void fwd_x_tile(const XGeom& g, const Stencil& st, co
     const int M = N ? N : g.M;
     const int nx = 2 * M;
     const int lb = g.lb;
+    using P = XLayout<N>;
     C* buf0 = reinterpret_cast<C*>(smem);
-    C* tw = buf0 + lb * M;  // exp(-2 pi i t / nx), t < nx
+    C* tw = buf0 + xbuf_span(lb * M);  // exp(-2 pi i t / nx), t < nx
     // staging area, 16-byte aligned (FP32 buffers may end on an 8-byte boundary)
     const size_t off = ((reinterpret_cast<size_t>(tw + 2 * M) - reinterpret_cast<size_t>(smem)) + 15) & ~size_t(15);
     unsigned char* rest = smem + off;
@@ -256,7 +273,7 @@ __device__ __forceinline__ void fwd_x_tile(const XGeom& g, const Stencil& st, co
             }
             if (a.r_out) reinterpret_cast<double2*>(a.r_out)[c2] = double2{v0, v1};
             rsum += v0 + v1;
-            buf0[line * M + n] = C{(TC)v0, (TC)v1};
+            buf0[P::at(line * M + n)] = C{(TC)v0, (TC)v1};
         }
     }
     if (MODE == FWD_METHOD3 && a.partials_abs) {
@@ -280,7 +297,7 @@ __device__ __forceinline__ void fwd_x_tile(const XGeom& g, const Stencil& st, co
         }
     }
     __syncthreads();
-    C* Z = lds_fft_n<N, -1, 2>(buf0, buf1, M, g.lb, M, g.rad, tw);
+    C* Z = lds_fft_n<N, -1, 2, P>(buf0, buf1, M, g.lb, M, g.rad, tw);
     // Split the half-length transform into the real-input spectrum:
     //   E_m = (Z_m + conj Z_{M-m}) / 2, O_m = (Z_m - conj Z_{M-m}) / (2i),
     //   X_m = E_m + exp(-2 pi i m / nx) O_m, m = 0..M.
@@ -289,8 +306,8 @@ __device__ __forceinline__ void fwd_x_tile(const XGeom& g, const Stencil& st, co
     for (int t = threadIdx.x; t < nout; t += 256) {
         const int m = t / g.lb;
         const int line = t - m * g.lb;
-        const C zm = Z[line * M + (m == M ? 0 : m)];
-        const C zc = cconj(Z[line * M + (m == 0 ? 0 : M - m)]);
+        const C zm = Z[P::at(line * M + (m == M ? 0 : m))];
+        const C zc = cconj(Z[P::at(line * M + (m == 0 ? 0 : M - m))]);
         const C e = C{(TC)0.5 * (zm.x + zc.x), (TC)0.5 * (zm.y + zc.y)};
         const C o = C{(TC)0.5 * (zm.y - zc.y), (TC)-0.5 * (zm.x - zc.x)};
         const C x = cadd(e, cmul(tw[m], o));
@@ -310,9 +327,10 @@ __device__ __forceinline__ void inv_x_tile(const XGeom& g, const c2<TC>* __restr
     const int k = b / g.tiles;
     const int j0 = (b - k * g.tiles) * g.lb;
     const int M = N ? N : g.M;
+    using P = XLayout<N>;
     C* buf0 = reinterpret_cast<C*>(smem);
-    C* xb = buf0 + g.lb * M;  // lb x (M+1), later reused as the FFT's second buffer
-    C* tw = xb + g.lb * (M + 1);
+    C* xb = buf0 + xbuf_span(g.lb * M);  // lb x (M+1), later reused as the FFT's second buffer
+    C* tw = xb + inv_x_stage_span(M, g.lb);
     for (int t = threadIdx.x; t < 2 * M; t += 256) tw[t] = tw_g[t];
     const size_t plane_s = (size_t)g.mx * g.ny;
     const int nin = (M + 1) * g.lb;
@@ -335,10 +353,10 @@ __device__ __forceinline__ void inv_x_tile(const XGeom& g, const c2<TC>* __restr
         const C e = C{(TC)0.5 * (xm.x + xc.x), (TC)0.5 * (xm.y + xc.y)};
         const C d = C{(TC)0.5 * (xm.x - xc.x), (TC)0.5 * (xm.y - xc.y)};
         const C o = cmul(d, cconj(tw[m]));
-        buf0[line * M + m] = C{e.x - o.y, e.y + o.x};
+        buf0[P::at(line * M + m)] = C{e.x - o.y, e.y + o.x};
     }
     __syncthreads();
-    C* z = lds_fft_n<N, +1, 2>(buf0, xb, M, g.lb, M, g.rad, tw);
+    C* z = lds_fft_n<N, +1, 2, P>(buf0, xb, M, g.lb, M, g.rad, tw);
     const double s = (MODE == INV_SCALE) ? scale * vol[k] : scale;
     // z_n = x_{2n} + i x_{2n+1}: one 16-byte store per pair of cells
     double2* out2 = reinterpret_cast<double2*>(out);
@@ -346,7 +364,7 @@ __device__ __forceinline__ void inv_x_tile(const XGeom& g, const c2<TC>* __restr
     for (int t = threadIdx.x; t < npair; t += 256) {
         const int line = t / M;
         const int n = t - line * M;
-        const C v = z[t];
+        const C v = z[P::at(t)];
         const size_t c2 = (((size_t)k * g.ny + j0 + line) * (2 * M)) / 2 + n;
         double2 x{(double)v.x * s, (double)v.y * s};
         if (MODE == INV_ADD) {

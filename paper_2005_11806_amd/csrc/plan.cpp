@@ -194,7 +194,8 @@ void plan_init(Plan& p, const psv_grid& g, const psv_opts& o, bool alloc_ws) {
     p.lp.lbx = 1;
     while (p.lp.lbx * 2 <= 16 && p.ny % (p.lp.lbx * 2) == 0 && x_lds_max(p.nx, p.lp.lbx * 2) <= budget)
         p.lp.lbx *= 2;
-    if (x_lds_max(p.nx, p.lp.lbx) > budget)
+    // one line per block may take up to the whole LDS (nx = 1024)
+    if (x_lds_max(p.nx, p.lp.lbx) > (size_t)std::min(lds_max, LDS_MAX_BLOCK))
         fail(PSV_ERR_UNSUPPORTED_SIZE, "line length exceeds the LDS budget");
     // chunk rows of the z partition: the largest of 16, 8, 4 whose y tile
     // takes at most 48 KiB of LDS (three blocks per CU), else the largest

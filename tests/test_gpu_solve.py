@@ -46,6 +46,8 @@ SHAPES = [
     ((96, 64, 24), True),   # 96 = 3 * 32
     ((8, 6, 2), False),     # smallest z
     ((64, 32, 40), True),
+    ((1024, 6, 5), True),   # longest x line: one line per block, over 64 KiB of LDS
+    ((768, 4, 4), False),   # runtime-length x FFT (M = 384) with over 64 KiB of LDS
 ]
 
 
