@@ -378,6 +378,8 @@ CONVERGED_WORKLOADS = {
                            "inside both loops"),
     "converged128_method1": ("fp64", "method1", "same problem with the Method-I weight min rho "
                              "in both loops; FP64"),
+    "converged128_method2": ("fp64", "method2", "same problem with the Method-II weight (harmonic "
+                             "mean of min and max rho) in both loops; FP64"),
 }
 
 
@@ -426,6 +428,62 @@ def bench_converged(args):
                    "converged": fi.converged and ai.converged,
                    "ms_per_iteration": ms / max(fi.iterations + ai.iterations, 1)},
         "roofline": traced_roofline(plan, step, spec),
+        "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
+METHODS2D_WORKLOADS = {
+    "bubble2d_methods": ("fp64", "128x256 x-z snapshot shaped like the rising-bubble case (one "
+                         "bubble of diameter 0.5 at (0.5, 0.5), density ratio 10): converged "
+                         "solves by Methods I, II and III to eps <= 1e-10 eps(0); value is "
+                         "Method III's rate, the config holds every method's iterations and time"),
+}
+
+
+def bench_methods2d(args):
+    """Converged solves of the 2-D rising-bubble snapshot by the three methods."""
+    import torch
+    import paper_2005_11806_amd as psv
+    import workloads as W
+    prec, desc = METHODS2D_WORKLOADS[args.workload]
+    case = W.rising_bubble_2d()
+    spec = case.grid
+    dev = torch.device("cuda:0")
+    to = lambda a: torch.from_numpy(a).to(dev)  # noqa: E731
+    plan = psv.Plan(psv.Grid.from_spec(spec), precision=prec, autotune=args.autotune)
+    f = plan.divergence(*(to(u) for u in case.faces))
+    rho = plan.density_from_colour(to(case.phi), to(case.rho_gas), case.rho_liq)
+    p = torch.empty(spec.nz, spec.ny, spec.nx, dtype=torch.float64, device=dev)
+    eps_t = 1e-10 * float(f.abs().sum())
+    per = {}
+    for it in ("method1", "method2", "method3"):
+        def step(it=it):
+            return plan.solve_converged(f, rho, iteration=it, eps_t=eps_t, max_iter=5000, out=p)[1]
+        info = step()
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        per[it] = {"iterations": info.iterations, "converged": info.converged,
+                   "ms": 1e3 * el / args.steps, "pts_per_s": spec.n * args.steps / el}
+    m3 = per["method3"]
+    line = {
+        "metric": METRIC, "value": m3["pts_per_s"], "unit": "grid_pts/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": m3["ms"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (seeded generators in workloads/)",
+        "config": {"workload": f"{args.workload}: {desc}", "grid": [spec.nx, spec.ny, spec.nz],
+                   "methods": per,
+                   "iterations_I_over_III": per["method1"]["iterations"] / m3["iterations"],
+                   "iterations_II_over_III": per["method2"]["iterations"] / m3["iterations"]},
+        "roofline": traced_roofline(
+            plan, lambda: plan.solve_converged(f, rho, iteration="method3", eps_t=eps_t,
+                                               max_iter=5000, out=p), spec),
         "cpu_baseline": None,
     }
     print(json.dumps(line), flush=True)
@@ -503,7 +561,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="vd128",
                     choices=sorted(WORKLOADS) + sorted(BATCH_WORKLOADS) + sorted(METHOD3_WORKLOADS)
-                    + sorted(GRAD_WORKLOADS) + sorted(CONVERGED_WORKLOADS))
+                    + sorted(GRAD_WORKLOADS) + sorted(CONVERGED_WORKLOADS)
+                    + sorted(METHODS2D_WORKLOADS))
     ap.add_argument("--mode", default="graph", choices=["graph", "eager"])
     ap.add_argument("--autotune", type=int, default=1, choices=[0, 1],
                     help="tune launch shapes at plan creation (outside the timed region)")
@@ -536,6 +595,9 @@ def main():
         return
     if args.workload in CONVERGED_WORKLOADS:
         bench_converged(args)
+        return
+    if args.workload in METHODS2D_WORKLOADS:
+        bench_methods2d(args)
         return
 
     if args.copy_probe:

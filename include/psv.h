@@ -182,15 +182,22 @@ psv_status psv_solve_method3(psv_plan* plan, const double* ux, const double* uy,
                              double* ux_out, double* uy_out, double* uz_out, void* stream,
                              psv_m3_info* info);
 
-/* The converged variable-density solve: the fixed point that Methods I and III
- * both iterate towards (Sec. 3.3.1; Eq. lap_p with f given directly),
+/* The converged variable-density solve: the fixed point that Methods I, II and
+ * III all iterate towards (Sec. 3.3.1; Eq. lap_p with f given directly),
  *     D(rho_f^-1 G p) = f - mean_V(f),
  * reached by iterating, in pressure form,
  *     p <- p + S[omega (f - mean_V(f) - D(rho_f^-1 G p))],
- * S the plan's eigenexpansion solve, with omega = min rho (PSV_ITER_METHOD1:
- * Eq. poisson_me1, robust at any density ratio, slow) or omega = rho in each
- * cell (PSV_ITER_METHOD3: Eq. new_poisson, fewer iterations; may diverge at
- * large density ratios on fine grids), until
+ * S the plan's eigenexpansion solve, with
+ *   PSV_ITER_METHOD1: omega = min rho (Eq. poisson_me1; robust at any density
+ *                     ratio, slow),
+ *   PSV_ITER_METHOD2: omega = 2 a b / (a + b), the harmonic mean of a = min rho
+ *                     and b = max rho, standing for the two phase densities
+ *                     (Eq. poisson_laizet; converges while max/min rho stays
+ *                     moderate),
+ *   PSV_ITER_METHOD3: omega = rho in each cell (Eq. new_poisson; fewest
+ *                     iterations; may diverge at large density ratios on
+ *                     fine grids),
+ * until
  *     eps = sum over cells of |f - mean_V(f) - D(rho_f^-1 G p)| <= eps_t
  * or max_iter solves. mean_V is the volume-weighted mean.
  *   f, rho [nz][ny][nx] device fields, rho > 0
@@ -202,7 +209,7 @@ psv_status psv_solve_method3(psv_plan* plan, const double* ux, const double* uy,
  * p = 0 (NaN when p_init is given). MIXED plans run FP32 solves inside the
  * loop, which corrects them. Stops without error at max_iter
  * (info->converged = 0). Synchronises every few iterations. */
-typedef enum { PSV_ITER_METHOD1 = 1, PSV_ITER_METHOD3 = 3 } psv_iteration;
+typedef enum { PSV_ITER_METHOD1 = 1, PSV_ITER_METHOD2 = 2, PSV_ITER_METHOD3 = 3 } psv_iteration;
 psv_status psv_solve_converged(psv_plan* plan, const double* f, const double* rho,
                                int32_t iteration, double eps_t, int32_t max_iter,
                                const double* p_init, double* p_out, void* stream,

@@ -9,7 +9,9 @@ III reaches it exactly, Eq. new_poisson) is the solution of Eq. lap_p,
 with rho_f the arithmetic mean of the two cells of a face. Both iterations
 are, in pressure form, p <- p + S[omega (f_c - A p)] with S the projected,
 gauged constant-coefficient solve and omega = rho0 = min rho (Method I,
-Eq. poisson_me1) or omega = rho (cell density, Method III).
+Eq. poisson_me1), omega = the harmonic mean of the two phase densities
+(Method II, Eq. poisson_laizet; read as those of min rho and max rho) or
+omega = rho (cell density, Method III).
 
 A is symmetric in the volume-weighted inner product (V A is symmetric), so
 for a loss sum(w p) the gradients are obtained from one more solve with the
@@ -60,9 +62,16 @@ class Converged:
 
 def solve(f, rho, grid, eps_t, max_iter, iteration="method3", p_init=None):
     """Iterate p <- p + S[omega (f_c - A p)] until sum |f_c - A p| <= eps_t or
-    max_iter solves; omega = rho (Method III) or min rho (Method I)."""
+    max_iter solves; omega = rho (Method III), min rho (Method I) or the
+    harmonic mean of min rho and max rho (Method II)."""
     fc = f - _vmean(f, grid)
-    omega = rho if iteration == "method3" else float(np.min(rho))
+    if iteration == "method3":
+        omega = rho
+    elif iteration == "method2":
+        a, b = float(np.min(rho)), float(np.max(rho))
+        omega = 2.0 * a * b / (a + b)
+    else:
+        omega = float(np.min(rho))
     p = np.zeros(grid.shape) if p_init is None else np.array(p_init, dtype=np.float64)
     eps = []
     for _ in range(max_iter + 1):

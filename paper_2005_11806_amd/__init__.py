@@ -82,7 +82,8 @@ class Method3Info:
 
 _PREC = {"fp64": _abi.PSV_FP64, "mixed": _abi.PSV_MIXED}
 _METH = {"const": _abi.PSV_CONST, "method1": _abi.PSV_SPLIT_RHO0}
-_ITER = {"method1": _abi.PSV_ITER_METHOD1, "method3": _abi.PSV_ITER_METHOD3}
+_ITER = {"method1": _abi.PSV_ITER_METHOD1, "method2": _abi.PSV_ITER_METHOD2,
+         "method3": _abi.PSV_ITER_METHOD3}
 
 
 def _iteration(name):
@@ -233,8 +234,8 @@ class Plan:
     def solve_converged(self, f, rho, iteration="method3", eps_t=0.0, max_iter=50, p_init=None,
                         out=None, stream=None):
         """Converged variable-density solve D(rho_f^-1 G p) = f - mean_V(f)
-        (psv_solve_converged). iteration: "method1" (weight min rho) or
-        "method3" (weight rho). Returns (p, Method3Info); eps is the summed
+        (psv_solve_converged). iteration: "method1" (weight min rho),
+        "method2" (harmonic mean of min and max rho) or "method3" (weight rho). Returns (p, Method3Info); eps is the summed
         absolute residual of that equation."""
         import torch
         sh = self.shape

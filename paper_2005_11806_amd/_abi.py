@@ -11,7 +11,7 @@ PSV_OK, PSV_ERR_INVALID_ARG, PSV_ERR_UNSUPPORTED_SIZE, PSV_ERR_HIP, PSV_ERR_NONF
     PSV_ERR_NOT_CONVERGED, PSV_ERR_OOM = range(7)
 PSV_FP64, PSV_MIXED = 0, 1
 PSV_CONST, PSV_SPLIT_RHO0 = 0, 1
-PSV_ITER_METHOD1, PSV_ITER_METHOD3 = 1, 3
+PSV_ITER_METHOD1, PSV_ITER_METHOD2, PSV_ITER_METHOD3 = 1, 2, 3
 PSV_BC_WALL_NEUMANN = 0
 
 STATUS_NAMES = {0: "PSV_OK", 1: "PSV_ERR_INVALID_ARG", 2: "PSV_ERR_UNSUPPORTED_SIZE", 3: "PSV_ERR_HIP",

@@ -437,13 +437,17 @@ static void converged_loop(Plan& P, const double* f, const double* scale, const 
     if (iteration == PSV_ITER_METHOD1) {
         psv::launch_min_reduce(P, rho, P.scal + psv::S_RHO0, P.flags + psv::F_ARGMIN, s);
         a.rho0 = P.scal + psv::S_RHO0;
+    } else if (iteration == PSV_ITER_METHOD2) {
+        psv::launch_harmonic_weight(P, rho, s);
+        a.rho0 = P.scal + psv::S_OMEGA;
     }
     residual_loop(P, fp32, a, 1.0, eps_t, max_iter, p_init, p_out, s);
 }
 
 static void need_loop_args(int32_t iteration, double eps_t, int32_t max_iter) {
-    need(iteration == PSV_ITER_METHOD1 || iteration == PSV_ITER_METHOD3,
-         "iteration must be PSV_ITER_METHOD1 or PSV_ITER_METHOD3");
+    need(iteration == PSV_ITER_METHOD1 || iteration == PSV_ITER_METHOD2 ||
+             iteration == PSV_ITER_METHOD3,
+         "iteration must be PSV_ITER_METHOD1, PSV_ITER_METHOD2 or PSV_ITER_METHOD3");
     need(std::isfinite(eps_t) && eps_t >= 0.0, "eps_t must be >= 0 and finite");
     need(max_iter >= 1 && max_iter <= 100000, "max_iter must be in [1, 100000]");
 }

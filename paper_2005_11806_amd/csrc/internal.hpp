@@ -65,6 +65,8 @@ enum Scalar : int {
     S_EPS0 = 8,        // Method III: the same for p = 0 (u = u*)
     S_FMEAN = 9,       // converged solve: volume-weighted mean of the right-hand side
     S_UNIT = 10,       // the constant 1 (weight of the implicit adjoint's face products)
+    S_RHOMAX = 11,     // max rho (Method II weight)
+    S_OMEGA = 12,      // Method II weight: harmonic mean of min rho and max rho
     S_NSCAL = 16
 };
 enum Flag : int { F_DONE = 0, F_ARGMIN = 1, F_STEPS = 2, F_CONV = 3, F_NFLAG = 8 };
@@ -189,6 +191,9 @@ void plan_set_kc(Plan& p, int kc);
 void launch_inv_x(const Plan& p, bool fp32, int mode, double* out, double scale_all,
                   const int* done, hipStream_t s);
 
+// Method II weight 2 a b / (a + b) of a = min rho, b = max rho into scal[S_OMEGA]
+// (also leaves them in scal[S_RHO0] and scal[S_RHOMAX]).
+void launch_harmonic_weight(const Plan& p, const double* rho, hipStream_t s);
 void launch_min_reduce(const Plan& p, const double* x, double* out_scalar, int* argmin_out,
                        hipStream_t s);
 void launch_norm_finalize(const Plan& p, int nblocks, double tol, hipStream_t s);

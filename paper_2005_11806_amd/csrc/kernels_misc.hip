@@ -65,6 +65,52 @@ __global__ void __launch_bounds__(RB) k_min_partial(const double* __restrict__ x
     }
 }
 
+// Largest value (no index), pairs of doubles, four in flight per thread.
+__global__ void __launch_bounds__(RB) k_max_partial(const double* __restrict__ x, size_t n,
+                                                    double* pv) {
+    __shared__ double sv[RB];
+    double best = -__builtin_inf();
+    constexpr int U = 4;
+    const double2* x2 = reinterpret_cast<const double2*>(x);
+    const size_t n2 = n / 2, stride = (size_t)gridDim.x * RB;
+    size_t c = (size_t)blockIdx.x * RB + threadIdx.x;
+    for (; c + (U - 1) * stride < n2; c += U * stride) {
+        double2 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = x2[c + u * stride];
+#pragma unroll
+        for (int u = 0; u < U; ++u) best = fmax(best, fmax(v[u].x, v[u].y));
+    }
+    for (; c < n2; c += stride) best = fmax(best, fmax(x2[c].x, x2[c].y));
+    if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) best = fmax(best, x[n - 1]);
+    sv[threadIdx.x] = best;
+    __syncthreads();
+    for (int o = RB / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) sv[threadIdx.x] = fmax(sv[threadIdx.x], sv[threadIdx.x + o]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) pv[blockIdx.x] = sv[0];
+}
+
+// scal[S_RHOMAX] = max of the partials; scal[S_OMEGA] = 2 a b / (a + b) with
+// a = scal[S_RHO0] (min rho), b = max rho.
+__global__ void __launch_bounds__(RB) k_harmonic_final(const double* pv, int nb, double* scal) {
+    __shared__ double sv[RB];
+    double best = -__builtin_inf();
+    for (int b = threadIdx.x; b < nb; b += RB) best = fmax(best, pv[b]);
+    sv[threadIdx.x] = best;
+    __syncthreads();
+    for (int o = RB / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) sv[threadIdx.x] = fmax(sv[threadIdx.x], sv[threadIdx.x + o]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double a = scal[S_RHO0], b = sv[0];
+        scal[S_RHOMAX] = b;
+        scal[S_OMEGA] = 2.0 * a * b / (a + b);
+    }
+}
+
 __global__ void __launch_bounds__(RB) k_min_final(const double* pv, const int* pi, int nb,
                                                   double* out, int* argmin) {
     __shared__ double sv[RB];
@@ -500,6 +546,14 @@ void launch_min_reduce(const Plan& p, const double* x, double* out_scalar, int* 
     TraceScope ts(p, "min_rho", s);
     hipLaunchKernelGGL(k_min_partial, dim3(nb), dim3(RB), 0, s, x, p.ncell(), pv, pi);
     hipLaunchKernelGGL(k_min_final, dim3(1), dim3(RB), 0, s, pv, pi, nb, out_scalar, argmin_out);
+    PSV_HIP(hipGetLastError());
+}
+
+void launch_harmonic_weight(const Plan& p, const double* rho, hipStream_t s) {
+    launch_min_reduce(p, rho, p.scal + S_RHO0, p.flags + F_ARGMIN, s);
+    const int nb = grid_blocks(p.ncell(), RB);
+    hipLaunchKernelGGL(k_max_partial, dim3(nb), dim3(RB), 0, s, rho, p.ncell(), p.partials);
+    hipLaunchKernelGGL(k_harmonic_final, dim3(1), dim3(RB), 0, s, p.partials, nb, p.scal);
     PSV_HIP(hipGetLastError());
 }
 

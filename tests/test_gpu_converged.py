@@ -1,5 +1,5 @@
 """GPU parity of the converged variable-density solve (psv_solve_converged:
-the common fixed point of Methods I and III, Sec. 3.3.1, Eq. lap_p) and its
+the common fixed point of Methods I, II and III, Sec. 3.3.1, Eq. lap_p) and its
 implicit adjoint (psv_solve_converged_adjoint) against the FP64 oracle's
 pressure-form iterations and adjoint, through the C ABI."""
 import numpy as np
@@ -28,7 +28,7 @@ def _case(shape, stretched, problem=1):
     return spec, g, f, rho, case.w
 
 
-@pytest.mark.parametrize("iteration", ["method1", "method3"])
+@pytest.mark.parametrize("iteration", ["method1", "method2", "method3"])
 @pytest.mark.parametrize("shape,stretched", SHAPES)
 def test_converged_iterates(gpu, shape, stretched, iteration):
     """Fixed iteration counts (eps_t = 0): every iterate at the FP64 tolerance.
@@ -49,7 +49,7 @@ def test_converged_iterates(gpu, shape, stretched, iteration):
         assert abs(info.eps_start - ref.eps[0]) <= 1e-12 * ref.eps[0]
 
 
-@pytest.mark.parametrize("iteration", ["method1", "method3"])
+@pytest.mark.parametrize("iteration", ["method1", "method2", "method3"])
 def test_converged_solution(gpu, iteration):
     spec, g, f, rho, _ = _case((32, 32, 32), True, 2)
     e0 = np.abs(f).sum()
@@ -155,11 +155,32 @@ def test_converged_input_errors(gpu):
     import ctypes
     out = torch.empty_like(F)
     st = lib.psv_solve_converged(plan._h, ctypes.c_void_p(F.data_ptr()), ctypes.c_void_p(R.data_ptr()),
-                                 2, 0.0, 3, None, ctypes.c_void_p(out.data_ptr()),
+                                 4, 0.0, 3, None, ctypes.c_void_p(out.data_ptr()),
                                  ctypes.c_void_p(torch.cuda.current_stream().cuda_stream), None)
     assert st == _abi.PSV_ERR_INVALID_ARG
     p, _ = plan.solve_converged(F, R, max_iter=2)
     with pytest.raises(psv.PsvError):   # grad_rho without p
         plan.converged_adjoint(dev(w), R, None, max_iter=2)
     with pytest.raises(ValueError):     # iteration from neither method
-        plan.converged_adjoint(dev(w), R, p, iteration="method2", max_iter=2)
+        plan.converged_adjoint(dev(w), R, p, iteration="method4", max_iter=2)
+
+
+def test_iteration_counts_rising_bubble(gpu):
+    """Methods I, II and III on the rising-bubble-shaped 2-D snapshot at the
+    paper's grid (128 x 256, density ratio 10): the GPU counts equal the
+    oracle's within one, III < II < I, and all reach one fixed point."""
+    case = W.rising_bubble_2d(128, 256)
+    g, f, rho, _ = oracle_inputs(case)
+    eps_t = 1e-10 * np.abs(f).sum()
+    plan = gpu.Plan(gpu.Grid.from_spec(case.grid))
+    F, R = dev(f), dev(rho)
+    counts, ps = {}, {}
+    for it in ("method1", "method2", "method3"):
+        ref = C.solve(f, rho, g, eps_t, 1000, it)
+        p, info = plan.solve_converged(F, R, iteration=it, eps_t=eps_t, max_iter=1000)
+        say(f"{it}: {info.iterations} solves (oracle {len(ref.eps) - 1})")
+        assert info.converged and abs(info.iterations - (len(ref.eps) - 1)) <= 1
+        counts[it], ps[it] = info.iterations, host(p)
+    assert counts["method3"] < counts["method2"] < counts["method1"]
+    for it in ("method1", "method2"):
+        assert rel_max_err(ps[it], ps["method3"]) <= 1e-8

@@ -38,7 +38,7 @@ RHO_LIQUID = 1000.0
  STREAM_DIVT) = range(8)
 
 CONFIG_IDS = {"const32": 0, "vd128": 1, "mixed_tanh": 2, "batch": 3, "grad256": 4, "method3": 5,
-              "converged": 6}
+              "converged": 6, "bubble2d": 7}
 
 BATCH_SHAPES = ((64, 64, 64), (96, 96, 128), (128, 128, 128), (128, 128, 192))
 
@@ -304,6 +304,25 @@ def converged_case(name: str, g: GridSpec, problem: int = 0, n_spheres: int = 20
 
 def converged_128(n: int = 128) -> Case:
     return converged_case("converged_128", uniform_grid(n, n, n), 0, 20)
+
+
+def rising_bubble_2d(nx: int = 128, nz: int = 256, rho_liq: float = 10.0,
+                     problem: int = 0) -> Case:
+    """Frozen snapshot shaped like the paper's rising-bubble case C2 (Sec. 4):
+    an x-z domain 1 x 2 (x periodic, walls in z, ny = 1), one circular gas
+    bubble of diameter 0.5 centred at (0.5, 0.5), Phi = (1 - tanh(d/eps))/2
+    with d the signed distance to the circle and eps = 1.5 dx, gas density 1
+    and liquid density rho_liq (density ratio 10 for the paper's first
+    temperature ratio). The right-hand side is the divergence of the seeded
+    face field; nothing of the paper's flow state is reproduced."""
+    g = GridSpec(nx, 1, nz, 1.0, 1.0 / nx, 2.0, None)
+    x, _, z = g.centres()
+    eps = 1.5 * g.lx / nx
+    d = np.sqrt((z[:, None, None] - 0.5) ** 2 + (x[None, None, :] - 0.5) ** 2) - 0.25
+    phi = 0.5 * (1.0 - np.tanh(d / eps))
+    faces = face_field(g, rng(CONFIG_IDS["bubble2d"], problem, STREAM_FACES))
+    return Case("rising_bubble_2d", g, faces, None, phi, np.ones((nz, 1, nx)), rho_liq, None,
+                None, 1)
 
 
 def fd_directions(config: int, n_dirs: int, shape) -> np.ndarray:
