@@ -88,6 +88,9 @@ typedef struct {
     int32_t chunk_rows;      /* rows per chunk of the wall-normal partition (planes per y
                                 tile): 0 automatic (tuned when autotune = 1), else 4, 8
                                 or 16 (PSV_ERR_UNSUPPORTED_SIZE if its tile does not fit) */
+    int32_t x_stencil;       /* neighbours of the forward x pass's stencil: 0 automatic
+                                (staged unless the autotuner finds direct loads faster),
+                                1 rows staged in LDS, 2 loaded directly (cache-served) */
 } psv_opts;
 
 typedef struct {

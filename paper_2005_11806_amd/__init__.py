@@ -82,6 +82,7 @@ class Method3Info:
 
 _PREC = {"fp64": _abi.PSV_FP64, "mixed": _abi.PSV_MIXED}
 _METH = {"const": _abi.PSV_CONST, "method1": _abi.PSV_SPLIT_RHO0}
+_XSTENCIL = {"auto": 0, "staged": 1, "direct": 2}
 _ITER = {"method1": _abi.PSV_ITER_METHOD1, "method2": _abi.PSV_ITER_METHOD2,
          "method3": _abi.PSV_ITER_METHOD3}
 
@@ -124,7 +125,7 @@ class Plan:
     """
 
     def __init__(self, grid: Grid, precision="fp64", method="method1", tol=1e-10,
-                 max_refine=4, check_inputs=False, autotune=0, chunk_rows=0):
+                 max_refine=4, check_inputs=False, autotune=0, chunk_rows=0, x_stencil="auto"):
         self.grid = grid
         self.precision = precision
         self.method = method
@@ -137,6 +138,7 @@ class Plan:
         o.check_inputs = int(bool(check_inputs))
         o.autotune = int(autotune)
         o.chunk_rows = int(chunk_rows)
+        o.x_stencil = _XSTENCIL[x_stencil]
         g, _keep = grid._c()
         h = C.c_void_p()
         check(lib().psv_plan_create(C.byref(g), C.byref(o), C.byref(h)))

@@ -29,7 +29,7 @@ class psv_grid(C.Structure):
 class psv_opts(C.Structure):
     _fields_ = [("precision", C.c_int), ("method", C.c_int), ("tol", C.c_double),
                 ("max_refine", C.c_int32), ("check_inputs", C.c_int32), ("autotune", C.c_int32),
-                ("batch_executor", C.c_int32), ("chunk_rows", C.c_int32)]
+                ("batch_executor", C.c_int32), ("chunk_rows", C.c_int32), ("x_stencil", C.c_int32)]
 
 
 class psv_info(C.Structure):

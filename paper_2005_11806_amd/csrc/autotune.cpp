@@ -35,6 +35,7 @@ std::string tune_key(const Plan& p) {
        << (p.opts.precision == PSV_MIXED ? "mixed" : "fp64") << ":"
        << (p.opts.method == PSV_SPLIT_RHO0 ? "method1" : "const");
     if (p.opts.chunk_rows) os << ":kc" << p.opts.chunk_rows;
+    if (p.opts.x_stencil) os << ":xs" << p.opts.x_stencil;
     return os.str();
 }
 
@@ -49,7 +50,16 @@ void load_cache() {
         std::istringstream ls(line);
         std::string key, extra;
         Launch l;
-        if ((ls >> key >> l.lbx >> l.kc) && !(ls >> extra)) g_cache[key] = l;
+        if (!(ls >> key >> l.lbx >> l.kc)) continue;
+        // entries may omit the inverse lines per block and the staging choice
+        if (!(ls >> l.lbx_inv)) {
+            l.lbx_inv = l.lbx;
+        } else if (!(ls >> l.xstage)) {
+            l.xstage = 1;
+        } else if (ls >> extra || (l.xstage != 0 && l.xstage != 1)) {
+            continue;
+        }
+        g_cache[key] = l;
     }
 }
 
@@ -58,7 +68,7 @@ void store_cache(const std::string& key, const Launch& l) {
     const char* path = std::getenv("PSV_AUTOTUNE_CACHE");
     if (!path) return;
     std::ofstream out(path, std::ios::app);
-    out << key << " " << l.lbx << " " << l.kc << "\n";
+    out << key << " " << l.lbx << " " << l.kc << " " << l.lbx_inv << " " << l.xstage << "\n";
 }
 
 // deterministic synthetic inputs: f, p_prev smooth-ish, rho in [1, 1000]
@@ -115,8 +125,11 @@ void autotune_plan(Plan& p) {
     auto it = g_cache.find(key);
     const bool kc_fixed = p.opts.chunk_rows != 0;
     if (it != g_cache.end()) {
-        if (fits_x(p, it->second.lbx) && kc_fits(p, it->second.kc)) {
+        if (fits_x(p, it->second.lbx) && fits_x(p, it->second.lbx_inv) &&
+            kc_fits(p, it->second.kc)) {
             p.lp.lbx = it->second.lbx;
+            p.lp.lbx_inv = it->second.lbx_inv;
+            p.lp.xstage = it->second.xstage;
             if (!kc_fixed && it->second.kc != p.lp.kc) plan_set_kc(p, it->second.kc);
             return;
         }
@@ -140,15 +153,31 @@ void autotune_plan(Plan& p) {
     solve_once(p, a, out_ref, s);
 
     Launch best = def;
-    float tbest = 1e30f;
+    // the two x passes read and write the spectrum in the same layout whatever
+    // their lines per block, so each takes its own
+    float tbest = 1e30f, tbest_inv = 1e30f;
     for (int lb : {1, 2, 4, 8, 16}) {
         if (!fits_x(p, lb)) continue;
         p.lp.lbx = lb;
-        const float t = time_ms(s, [&] { launch_fwd_x(p, fp32, a, s); }) +
-                        time_ms(s, [&] { launch_inv_x(p, fp32, INV_STORE, out, 1.0, nullptr, s); });
-        if (t < tbest) { tbest = t; best.lbx = lb; }
+        p.lp.lbx_inv = lb;
+        for (int stage : {1, 0}) {
+            if (p.opts.x_stencil && stage != def.xstage) continue;  // fixed by the caller
+            p.lp.xstage = stage;
+            // timed together with the z solve, which evicts the inputs from the
+            // caches as a solve does: back to back, the forward pass alone would
+            // find its inputs cached and favour the direct loads
+            const float t = time_ms(s, [&] {
+                launch_fwd_x(p, fp32, a, s);
+                launch_z_solve(p, fp32, p.scal + S_MEAN2, nullptr, s);
+            });
+            if (t < tbest) { tbest = t; best.lbx = lb; best.xstage = stage; }
+        }
+        const float ti = time_ms(s, [&] { launch_inv_x(p, fp32, INV_STORE, out, 1.0, nullptr, s); });
+        if (ti < tbest_inv) { tbest_inv = ti; best.lbx_inv = lb; }
     }
     p.lp.lbx = best.lbx;
+    p.lp.lbx_inv = best.lbx_inv;
+    p.lp.xstage = best.xstage;
     tbest = 1e30f;
     for (int kc : {4, 8, 16}) {
         if (!kc_fits(p, kc) || kc > 2 * p.nz || (kc_fixed && kc != def.kc)) continue;
@@ -179,7 +208,8 @@ void autotune_plan(Plan& p) {
         p.lp = def;
         plan_set_kc(p, def.kc);
     } else if (std::getenv("PSV_LOG")) {
-        std::fprintf(stderr, "psv autotune: %s -> lbx %d kc %d\n", key.c_str(), p.lp.lbx, p.lp.kc);
+        std::fprintf(stderr, "psv autotune: %s -> lbx %d kc %d lbx_inv %d xstage %d\n", key.c_str(),
+                     p.lp.lbx, p.lp.kc, p.lp.lbx_inv, p.lp.xstage);
     }
     store_cache(key, p.lp);
     (void)hipStreamDestroy(s);

@@ -473,7 +473,8 @@ void plan_free(Plan& p);
 
 static size_t kind_lds(const Plan& p, int kind, bool fp32) {
     const size_t cs = fp32 ? sizeof(float2) : sizeof(double2);
-    const XGeom g = make_xgeom(p);
+    XGeom g = make_xgeom(p);
+    g.stage = 1;  // batch tiles stage the stencil rows
     switch (kind) {
         case K_FWD: case K_RES: return fwd_x_lds(g, cs);
         case K_INV: case K_INVADD: return inv_x_lds(g, cs);
@@ -632,6 +633,7 @@ void batch_create(psv_batch& B, int n, const psv_grid* grids, const psv_opts& o)
         ProblemDesc& D = desc[p];
         std::memset(&D, 0, sizeof(D));
         D.xg = make_xgeom(*pl);
+        D.xg.stage = 1;
         D.st = Stencil{pl->t.inv_h, pl->t.inv_g, pl->t.vol};
         D.z = make_zargs(*pl, pl->scal + S_RHS_MEAN);
         D.method = o.method;

@@ -91,8 +91,10 @@ struct DevTables {
 };
 
 struct Launch {
-    int lbx = 8;  // lines per block, x passes
-    int kc = 8;   // planes per y tile = rows per chunk of the z partition
+    int lbx = 8;      // lines per block, forward x pass (and both x passes of batches)
+    int kc = 8;       // planes per y tile = rows per chunk of the z partition
+    int lbx_inv = 8;  // lines per block, inverse x pass of a plan
+    int xstage = 1;   // forward x pass of a plan: stencil rows staged in LDS (1) or read directly (0)
 };
 
 // Launch-shape autotuning (autotune.cpp): times candidate shapes per pass on

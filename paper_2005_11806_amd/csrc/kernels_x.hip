@@ -5,15 +5,15 @@
 namespace psv {
 namespace {
 
-template <typename TC, typename TS, int MODE, int N>
+template <typename TC, typename TS, int MODE, int N, bool STAGE>
 __global__ void __launch_bounds__(256) k_fwd_x(XGeom g, Stencil st, FwdArgs a,
                                                 const c2<TC>* __restrict__ tw_g,
                                                 c2<TS>* __restrict__ spec) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ double red[16];
     if (a.done && *a.done) return;
-    fwd_x_tile<TC, TS, MODE, N>(g, st, a, tw_g, spec, xcd_remap(blockIdx.x, gridDim.x), smem_raw,
-                                red);
+    fwd_x_tile<TC, TS, MODE, N, STAGE>(g, st, a, tw_g, spec, xcd_remap(blockIdx.x, gridDim.x),
+                                       smem_raw, red);
 }
 
 template <typename TC, typename TS, int MODE, int N>
@@ -31,14 +31,23 @@ __global__ void __launch_bounds__(256) k_inv_x(XGeom g, const c2<TC>* __restrict
 // x-line lengths with a compile-time FFT (M = nx/2); others use the runtime one
 #define PSV_X_SIZES(X) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(512)
 
+template <typename TC, typename TS, int MODE, int N, bool STAGE>
+void fwd_launch_s(const Plan& p, const XGeom& g, const Stencil& st, const FwdArgs& a,
+                  const c2<TC>* tw, hipStream_t s) {
+    const size_t lds = fwd_x_lds(g, sizeof(c2<TC>));
+    allow_lds(k_fwd_x<TC, TS, MODE, N, STAGE>, lds);
+    hipLaunchKernelGGL((k_fwd_x<TC, TS, MODE, N, STAGE>), dim3(g.tiles * p.nz), dim3(256), lds, s,
+                       g, st, a, tw, reinterpret_cast<c2<TS>*>(p.spec));
+}
+
+// the constant-coefficient copy has no stencil: one variant
 template <typename TC, typename TS, int MODE, int N>
 void fwd_launch(const Plan& p, const XGeom& g, const Stencil& st, const FwdArgs& a,
                 const c2<TC>* tw, hipStream_t s) {
-    const size_t lds = fwd_x_lds(g, sizeof(c2<TC>));
-    allow_lds(k_fwd_x<TC, TS, MODE, N>, lds);
-    hipLaunchKernelGGL((k_fwd_x<TC, TS, MODE, N>), dim3(g.tiles * p.nz), dim3(256), lds, s, g,
-                       st, a, tw,
-                       reinterpret_cast<c2<TS>*>(p.spec));
+    if (MODE == FWD_CONST || g.stage)
+        fwd_launch_s<TC, TS, MODE, N, true>(p, g, st, a, tw, s);
+    else
+        fwd_launch_s<TC, TS, MODE, N, MODE == FWD_CONST>(p, g, st, a, tw, s);
 }
 
 template <typename TC, typename TS, int MODE>
@@ -71,7 +80,7 @@ void inv_launch(const Plan& p, const XGeom& g, const c2<TC>* tw, double* out, do
 
 template <typename TC, typename TS, int MODE>
 void inv_impl(const Plan& p, double* out, double scale, const int* done, hipStream_t s) {
-    XGeom g = make_xgeom(p);
+    XGeom g = make_xgeom(p, true);
     const c2<TC>* tw;
     if constexpr (sizeof(TC) == 8) tw = p.t.twx64; else tw = p.t.twx32;
     static const char* names[2][3] = {{"inv_x_store_fp64", "inv_x_add_fp64", "inv_x_scale_fp64"},

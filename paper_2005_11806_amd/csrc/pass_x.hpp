@@ -17,6 +17,7 @@ namespace psv {
 
 struct XGeom {
     int nx, ny, nz, mx, M, lb, tiles;  // tiles = ny / lb
+    int stage;                         // forward tile: stencil rows staged in LDS (1) or not (0)
     double inv_dx, inv_dy;
     Radices rad;
 };
@@ -36,15 +37,15 @@ using XLayout = std::conditional_t<(N > 0), Pad8, NoPad>;
 __host__ __device__ inline int xbuf_span(int n) { return n + (n >> 3) + 1; }
 
 // LDS bytes of the x tiles for complex element size csz. Forward: FFT buffer,
-// twiddles, then either the second FFT buffer or the staged rows of p and rho
-// (lb + 2 rows each, FP64), which the second buffer reuses after assembly.
-// Inverse: FFT buffer, the staged half spectrum (lb x (M+1), reused as the
-// second FFT buffer), twiddles.
-inline size_t fwd_x_lds_n(int nx, int lb, size_t csz) {
+// twiddles, then the second FFT buffer, which with `stage` shares its space
+// with the staged rows of p and rho (lb + 2 rows each, FP64) read by the
+// stencil before the transform. Inverse: FFT buffer, the staged half
+// spectrum (lb x (M+1), reused as the second FFT buffer), twiddles.
+inline size_t fwd_x_lds_n(int nx, int lb, size_t csz, bool stage = true) {
     const size_t M = nx / 2;
-    const size_t stage = (size_t)2 * (lb + 2) * nx * sizeof(double);
+    const size_t rows = stage ? (size_t)2 * (lb + 2) * nx * sizeof(double) : 0;
     const size_t buf = (size_t)xbuf_span(lb * (int)M) * csz;
-    return buf + 2 * M * csz + 16 + (stage > buf ? stage : buf);
+    return buf + 2 * M * csz + 16 + (rows > buf ? rows : buf);
 }
 __host__ __device__ inline int inv_x_stage_span(int M, int lb) {
     const int a = lb * (M + 1), b = xbuf_span(lb * M);
@@ -54,9 +55,10 @@ inline size_t inv_x_lds_n(int nx, int lb, size_t csz) {
     const int M = nx / 2;
     return ((size_t)xbuf_span(lb * M) + inv_x_stage_span(M, lb) + 2 * (size_t)M) * csz;
 }
-inline size_t fwd_x_lds(const XGeom& g, size_t csz) { return fwd_x_lds_n(g.nx, g.lb, csz); }
+inline size_t fwd_x_lds(const XGeom& g, size_t csz) { return fwd_x_lds_n(g.nx, g.lb, csz, g.stage != 0); }
 inline size_t inv_x_lds(const XGeom& g, size_t csz) { return inv_x_lds_n(g.nx, g.lb, csz); }
-// the larger of the two at FP64, for choosing lines per block
+// the larger of the two at FP64 (forward with staged rows), for choosing lines
+// per block
 inline size_t x_lds_max(int nx, int lb) {
     const size_t a = fwd_x_lds_n(nx, lb, 16), b = inv_x_lds_n(nx, lb, 16);
     return a > b ? a : b;
@@ -106,7 +108,7 @@ __device__ __forceinline__ double lap_cell(const double* __restrict__ p, int i, 
 // Forward tile b. N = nx/2 as a compile-time constant, or 0 (runtime length).
 // Partial sums (when requested) go to a.partials at slot b: one value
 // (vol * sum r) for CONST/METHOD1, two (sum res^2, sum r~^2) for RESID.
-template <typename TC, typename TS, int MODE, int N>
+template <typename TC, typename TS, int MODE, int N, bool STAGE = true>
 __device__ __forceinline__ void fwd_x_tile(const XGeom& g, const Stencil& st, const FwdArgs& a,
                                            const c2<TC>* __restrict__ tw_g,
                                            c2<TS>* __restrict__ spec, int b, unsigned char* smem,
@@ -120,12 +122,12 @@ __device__ __forceinline__ void fwd_x_tile(const XGeom& g, const Stencil& st, co
     using P = XLayout<N>;
     C* buf0 = reinterpret_cast<C*>(smem);
     C* tw = buf0 + xbuf_span(lb * M);  // exp(-2 pi i t / nx), t < nx
-    // staging area, 16-byte aligned (FP32 buffers may end on an 8-byte boundary)
+    // second FFT buffer, 16-byte aligned (FP32 buffers may end on an 8-byte
+    // boundary); with STAGE it first holds the p and rho rows j0-1 .. j0+lb
     const size_t off = ((reinterpret_cast<size_t>(tw + 2 * M) - reinterpret_cast<size_t>(smem)) + 15) & ~size_t(15);
-    unsigned char* rest = smem + off;
-    C* buf1 = reinterpret_cast<C*>(rest);       // second FFT buffer, used after assembly
-    double2* pt = reinterpret_cast<double2*>(rest);  // staged p rows j0-1 .. j0+lb (periodic)
-    double2* rt = pt + (lb + 2) * M;                 // staged rho rows (Method I)
+    C* buf1 = reinterpret_cast<C*>(smem + off);
+    double2* pt = reinterpret_cast<double2*>(smem + off);  // staged p rows (periodic in y)
+    double2* rt = pt + (lb + 2) * M;                        // staged rho rows
     for (int t = threadIdx.x; t < 2 * M; t += 256) tw[t] = tw_g[t];
     const size_t plane = (size_t)nx * g.ny;
 
@@ -146,13 +148,20 @@ __device__ __forceinline__ void fwd_x_tile(const XGeom& g, const Stencil& st, co
     const bool has_p = MODE != FWD_METHOD3 || a.pprev != nullptr;
     // One thread per pair of cells (2n, 2n+1): exactly the packed input
     // z_n = r_{2n} + i r_{2n+1} of the half-length transform. The global
-    // operands of a thread's next PF pairs (f or r_in, and p, rho on the
-    // planes k +- 1) are loaded into registers together; the first batch is
-    // issued before the row staging, so the two loads overlap.
+    // operands of a thread's next PF pairs are loaded into registers together:
+    // with STAGE, f (or r_in) and p, rho on the planes k +- 1, issued before
+    // the rows j0-1 .. j0+lb of p and rho are staged in LDS for the in-plane
+    // neighbours, so the two loads overlap; without, every operand (the pair,
+    // its y and z neighbour pairs and its two x neighbours), where the caches
+    // serve the rows that neighbouring pairs and tiles share. The autotuner
+    // picks the faster of the two per grid.
     struct Pre {
-        double2 f, ptz, pbz, rtz, rbz;
+        double2 f, pc, pn, ps, ptz, pbz, rc, rn, rs, rtz, rbz;
+        double pw, pe, rw, re;
     };
-    constexpr int PF = 2;
+    constexpr int PF = (MODE == FWD_CONST || STAGE) ? 2 : 1;
+    const double* pd = a.pprev;
+    const double* rd = a.rho;
     const int npair = lb * M;
     const double2* fg = reinterpret_cast<const double2*>(MODE == FWD_RESID ? a.r_in : a.f);
     const double2* pg = reinterpret_cast<const double2*>(a.pprev);
@@ -165,25 +174,55 @@ __device__ __forceinline__ void fwd_x_tile(const XGeom& g, const Stencil& st, co
 #pragma unroll
         for (int u = 0; u < PF; ++u) {
             const int t = t0 + u * 256;
-            pre[u].ptz = pre[u].pbz = double2{0.0, 0.0};
-            pre[u].rtz = pre[u].rbz = double2{1.0, 1.0};
+            Pre& q = pre[u];
+            q.pc = q.pn = q.ps = q.ptz = q.pbz = double2{0.0, 0.0};
+            q.rc = q.rn = q.rs = q.rtz = q.rbz = double2{1.0, 1.0};
+            q.pw = q.pe = 0.0;
+            q.rw = q.re = 1.0;
             if (t < npair) {
                 const size_t c2 = pair_index(t);
-                pre[u].f = fg[c2];
-                if (MODE != FWD_CONST && has_p) {
-                    if (has_t) pre[u].ptz = pg[c2 + plane / 2];
-                    if (has_b) pre[u].pbz = pg[c2 - plane / 2];
-                }
-                if (MODE == FWD_METHOD1 || MODE == FWD_METHOD3) {
-                    if (has_t) pre[u].rtz = rg[c2 + plane / 2];
-                    if (has_b) pre[u].rbz = rg[c2 - plane / 2];
+                q.f = fg[c2];
+                if (MODE != FWD_CONST && STAGE) {
+                    if (has_p) {
+                        if (has_t) q.ptz = pg[c2 + plane / 2];
+                        if (has_b) q.pbz = pg[c2 - plane / 2];
+                    }
+                    if (MODE == FWD_METHOD1 || MODE == FWD_METHOD3) {
+                        if (has_t) q.rtz = rg[c2 + plane / 2];
+                        if (has_b) q.rbz = rg[c2 - plane / 2];
+                    }
+                } else if (MODE != FWD_CONST) {
+                    const int line = t / M, n = t - line * M, j = j0 + line;
+                    // neighbour pairs in y (periodic) and cells in x (periodic in the line)
+                    const size_t cn = c2 + (size_t)((j + 1 == g.ny) ? -(g.ny - 1) * M : M);
+                    const size_t cs = c2 - (size_t)((j == 0) ? -(g.ny - 1) * M : M);
+                    const size_t xw = 2 * c2 + (n == 0 ? nx - 1 : -1);
+                    const size_t xe = 2 * c2 + (n + 1 == M ? 2 - nx : 2);
+                    if (has_p) {
+                        q.pc = pg[c2];
+                        q.pn = pg[cn];
+                        q.ps = pg[cs];
+                        q.pw = pd[xw];
+                        q.pe = pd[xe];
+                        if (has_t) q.ptz = pg[c2 + plane / 2];
+                        if (has_b) q.pbz = pg[c2 - plane / 2];
+                    }
+                    if (MODE == FWD_METHOD1 || MODE == FWD_METHOD3) {
+                        q.rc = rg[c2];
+                        q.rn = rg[cn];
+                        q.rs = rg[cs];
+                        q.rw = rd[xw];
+                        q.re = rd[xe];
+                        if (has_t) q.rtz = rg[c2 + plane / 2];
+                        if (has_b) q.rbz = rg[c2 - plane / 2];
+                    }
                 }
             }
         }
     };
     Pre cur[PF];
     prefetch(threadIdx.x, cur);
-    if (MODE != FWD_CONST) {
+    if (MODE != FWD_CONST && STAGE) {
         for (int t = threadIdx.x; t < (lb + 2) * M; t += 256) {
             const int rr = t / M;
             const int q = t - rr * M;
@@ -195,6 +234,41 @@ __device__ __forceinline__ void fwd_x_tile(const XGeom& g, const Stencil& st, co
         }
         __syncthreads();
     }
+    // in-plane neighbours of pair n of a line: from the staged rows or the registers
+    auto p_nb = [&](const Pre& q, int line, int n, double2& pc, double2& pn, double2& ps, double& pw,
+                    double& pe) {
+        if constexpr (STAGE) {
+            const double2* Pr = pt + (line + 1) * M;
+            pc = Pr[n];
+            pn = Pr[n + M];
+            ps = Pr[n - M];
+            pw = Pr[n == 0 ? M - 1 : n - 1].y;
+            pe = Pr[n + 1 == M ? 0 : n + 1].x;
+        } else {
+            pc = q.pc;
+            pn = q.pn;
+            ps = q.ps;
+            pw = q.pw;
+            pe = q.pe;
+        }
+    };
+    auto r_nb = [&](const Pre& q, int line, int n, double2& rc, double2& rn, double2& rs, double& rw,
+                    double& re) {
+        if constexpr (STAGE) {
+            const double2* Rr = rt + (line + 1) * M;
+            rc = Rr[n];
+            rn = Rr[n + M];
+            rs = Rr[n - M];
+            rw = Rr[n == 0 ? M - 1 : n - 1].y;
+            re = Rr[n + 1 == M ? 0 : n + 1].x;
+        } else {
+            rc = q.rc;
+            rn = q.rn;
+            rs = q.rs;
+            rw = q.rw;
+            re = q.re;
+        }
+    };
     for (int t0 = threadIdx.x; t0 < npair; t0 += PF * 256) {
         if (t0 != (int)threadIdx.x) prefetch(t0, cur);
 #pragma unroll
@@ -210,14 +284,14 @@ __device__ __forceinline__ void fwd_x_tile(const XGeom& g, const Stencil& st, co
                 v0 = q.f.x * sc;
                 v1 = q.f.y * sc;
             } else {
-                const double2* P = pt + (line + 1) * M;
-                const double2 pc = P[n], pn = P[n + M], ps = P[n - M];
-                const double pw = P[n == 0 ? M - 1 : n - 1].y, pe = P[n + 1 == M ? 0 : n + 1].x;
+                double2 pc, pn, ps;
+                double pw, pe;
+                p_nb(q, line, n, pc, pn, ps, pw, pe);
                 const double2 ptz = q.ptz, pbz = q.pbz;
                 if (MODE == FWD_METHOD1) {
-                    const double2* R = rt + (line + 1) * M;
-                    const double2 rc = R[n], rn = R[n + M], rs = R[n - M];
-                    const double rw = R[n == 0 ? M - 1 : n - 1].y, re = R[n + 1 == M ? 0 : n + 1].x;
+                    double2 rc, rn, rs;
+                    double rw, re;
+                    r_nb(q, line, n, rc, rn, rs, rw, re);
                     const double2 rtz = q.rtz, rbz = q.rbz;
                     // x faces: west of 2n, between the pair, east of 2n+1
                     const double fw = bflux(rw, rc.x, pw, pc.x, two_r0);
@@ -237,9 +311,9 @@ __device__ __forceinline__ void fwd_x_tile(const XGeom& g, const Stencil& st, co
                 } else if (MODE == FWD_METHOD3) {
                     // q = f - D(rho_f^-1 G p), r = rho q (cell density, Eq. new_poisson in
                     // pressure form)
-                    const double2* R = rt + (line + 1) * M;
-                    const double2 rc = R[n], rn = R[n + M], rs = R[n - M];
-                    const double rw = R[n == 0 ? M - 1 : n - 1].y, re = R[n + 1 == M ? 0 : n + 1].x;
+                    double2 rc, rn, rs;
+                    double rw, re;
+                    r_nb(q, line, n, rc, rn, rs, rw, re);
                     const double2 rtz = q.rtz, rbz = q.rbz;
                     const double fw = gflux(rw, rc.x, pw, pc.x);
                     const double fm = gflux(rc.x, rc.y, pc.x, pc.y);
@@ -376,15 +450,17 @@ __device__ __forceinline__ void inv_x_tile(const XGeom& g, const c2<TC>* __restr
     }
 }
 
-inline XGeom make_xgeom(const Plan& p) {
+// Geometry of the x tiles; `inverse` selects the inverse pass's lines per block.
+inline XGeom make_xgeom(const Plan& p, bool inverse = false) {
     XGeom g;
     g.nx = p.nx;
     g.ny = p.ny;
     g.nz = p.nz;
     g.mx = p.mx;
     g.M = p.nx / 2;
-    g.lb = p.lp.lbx;
-    g.tiles = p.ny / p.lp.lbx;
+    g.lb = inverse ? p.lp.lbx_inv : p.lp.lbx;
+    g.tiles = p.ny / g.lb;
+    g.stage = p.lp.xstage;
     g.inv_dx = 1.0 / p.dx;
     g.inv_dy = 1.0 / p.dy;
     g.rad = p.rad_xh;

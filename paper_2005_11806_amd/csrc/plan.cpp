@@ -79,6 +79,7 @@ void validate_opts(const psv_opts* o) {
         fail(PSV_ERR_INVALID_ARG, "batch_executor must be 0..2");
     if (o->chunk_rows != 0 && o->chunk_rows != 4 && o->chunk_rows != 8 && o->chunk_rows != 16)
         fail(PSV_ERR_INVALID_ARG, "chunk_rows must be 0, 4, 8 or 16");
+    if (o->x_stencil < 0 || o->x_stencil > 2) fail(PSV_ERR_INVALID_ARG, "x_stencil must be 0..2");
 }
 
 void default_opts(psv_opts* o) {
@@ -91,6 +92,7 @@ void default_opts(psv_opts* o) {
     o->autotune = 0;
     o->batch_executor = 0;
     o->chunk_rows = 0;
+    o->x_stencil = 0;
 }
 
 // exp(-2 pi i t / n), t = 0..n-1, from the angle reduced to the first octant
@@ -197,6 +199,8 @@ void plan_init(Plan& p, const psv_grid& g, const psv_opts& o, bool alloc_ws) {
     // one line per block may take up to the whole LDS (nx = 1024)
     if (x_lds_max(p.nx, p.lp.lbx) > (size_t)std::min(lds_max, LDS_MAX_BLOCK))
         fail(PSV_ERR_UNSUPPORTED_SIZE, "line length exceeds the LDS budget");
+    p.lp.lbx_inv = p.lp.lbx;
+    p.lp.xstage = p.opts.x_stencil == 2 ? 0 : 1;
     // chunk rows of the z partition: the largest of 16, 8, 4 whose y tile
     // takes at most 48 KiB of LDS (three blocks per CU), else the largest
     // that fits a block at all

@@ -32,7 +32,7 @@ def test_library_exports_every_declared_function():
 
 def test_struct_layouts_match_header():
     assert C.sizeof(_abi.psv_grid) == 3 * 4 + 4 + 3 * 8 + 8 + 8  # ints, pad, doubles, ptr, enum+pad
-    assert C.sizeof(_abi.psv_opts) == 8 + 8 + 5 * 4 + 4  # precision, method, tol, 5 ints, pad
+    assert C.sizeof(_abi.psv_opts) == 8 + 8 + 6 * 4  # precision, method, tol, 6 ints
     assert C.sizeof(_abi.psv_info) == 8 + 3 * 8
 
 
@@ -90,6 +90,11 @@ def test_plan_create_rejects_before_device_work():
     o.chunk_rows = 12  # only 4, 8 or 16
     assert lib.psv_plan_create(C.byref(g2), C.byref(o), C.byref(h)) == _abi.PSV_ERR_INVALID_ARG
     assert b"chunk_rows" in lib.psv_last_error_message()
+    lib.psv_opts_default(C.byref(o))
+    assert o.x_stencil == 0
+    o.x_stencil = 3  # only 0, 1 or 2
+    assert lib.psv_plan_create(C.byref(g2), C.byref(o), C.byref(h)) == _abi.PSV_ERR_INVALID_ARG
+    assert b"x_stencil" in lib.psv_last_error_message()
     assert lib.psv_plan_create(C.byref(g2), None, None) == _abi.PSV_ERR_INVALID_ARG
     assert lib.psv_plan_shape(None, None, None) == _abi.PSV_ERR_INVALID_ARG
 

@@ -125,3 +125,16 @@ def test_method3_input_errors(gpu):
         plan.solve_method3(U, T, R, -1.0)
     with pytest.raises(psv.PsvError):
         plan.solve_method3(U, T, R, case.dt, max_iter=0)
+
+
+def test_method3_direct_stencil(gpu):
+    """Method III iterates with the forward pass reading its neighbours directly."""
+    spec = W.GridSpec(24, 18, 20, 1.0, 1.0, 20 / 24, W.tanh_faces(20, 20 / 24, 1.5))
+    case = W.method3_case("m3d", spec, 7, n_spheres=4)
+    g, faces, rho = _inputs(case)
+    ref = M3.solve(faces, case.div_target, rho, case.dt, g, eps_t=0.0, max_iter=3)
+    plan = gpu.Plan(gpu.Grid.from_spec(spec), x_stencil="direct")
+    p, _, info = plan.solve_method3(_dev_faces(faces), dev(case.div_target), dev(rho), case.dt,
+                                    eps_t=0.0, max_iter=3)
+    assert rel_max_err(host(p), ref.p[2]) <= TOL_FP64
+    assert abs(info.eps - ref.eps[2]) <= 1e-8 * ref.eps[2]
