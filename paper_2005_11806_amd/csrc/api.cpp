@@ -358,13 +358,22 @@ static void residual_loop(Plan& P, bool fp32, psv::FwdArgs a, double eps_scale, 
     double* qpart = P.partials + nb;  // sum |q| per block
     const double inv_scale = 2.0 / ((double)P.nx * P.ny);
     const int* done = P.flags + psv::F_DONE;
-    constexpr int ITER_PER_SYNC = 4;
+    // Iterations launched between two looks at the flag: a few at first, then
+    // as many as the contraction seen between the last two looks predicts to
+    // reach eps_t (plus one), at most MAX_BATCH; with eps_t = 0 the loop runs
+    // to max_iter.
+    constexpr int FIRST_BATCH = 4, MAX_BATCH = 32;
     a.mode = psv::FWD_METHOD3;
     a.partials_abs = qpart;
     a.done = done;
     psv::launch_m3_reset(P, s);
+    int batch = eps_t > 0.0 ? FIRST_BATCH : MAX_BATCH;
+    double prev_eps = 0.0;
+    int prev_steps = -1;
+    // max_iter solves and one last residual test need at most max_iter + 1 launches
     for (int launched = 0;;) {
-        for (int b = 0; b < ITER_PER_SYNC; ++b, ++launched) {
+        batch = std::max(1, std::min(batch, max_iter + 1 - launched));
+        for (int b = 0; b < batch; ++b, ++launched) {
             a.pprev = has_p ? p_out : nullptr;
             psv::launch_fwd_x(P, fp32, a, s);
             psv::launch_m3_check(P, qpart, nb, eps_scale, eps_t, has_p, max_iter, s);
@@ -375,9 +384,18 @@ static void residual_loop(Plan& P, bool fp32, psv::FwdArgs a, double eps_scale, 
         }
         sync_read(P, s);
         if (P.host_flags[psv::F_DONE]) break;
-        if (!std::isfinite(P.host_scal[psv::S_EPS]))
-            psv::fail(PSV_ERR_NONFINITE, "iteration residual is not finite");
-        if (launched > max_iter + 1) psv::fail(PSV_ERR_HIP, "iteration loop control failed");
+        const double eps = P.host_scal[psv::S_EPS];
+        if (!std::isfinite(eps)) psv::fail(PSV_ERR_NONFINITE, "iteration residual is not finite");
+        if (launched >= max_iter + 1) psv::fail(PSV_ERR_HIP, "iteration loop control failed");
+        const int steps = P.host_flags[psv::F_STEPS];
+        batch = eps_t > 0.0 ? FIRST_BATCH : MAX_BATCH;
+        if (eps_t > 0.0 && prev_steps >= 0 && steps > prev_steps && eps > 0.0 && eps < prev_eps) {
+            const double rate = std::pow(eps / prev_eps, 1.0 / (steps - prev_steps));
+            const double need = std::log(eps_t / eps) / std::log(rate);
+            batch = (int)std::min<double>(MAX_BATCH, std::max(1.0, std::ceil(need) + 1.0));
+        }
+        prev_eps = eps;
+        prev_steps = steps;
     }
 }
 
