@@ -157,7 +157,9 @@ psv_status psv_solve_adjoint(psv_plan* plan, const double* w, const double* f, c
  * in every cell, and p solves div(rho^-1 grad p) = (div u* - div_target)/dt.
  * Each iteration is the eigenexpansion solve of the plan (FP64, or FP32 for a
  * MIXED plan: the loop itself corrects the FP32 solves). Uses the plan's
- * workspace; synchronises once per iteration to read eps.
+ * workspace. The residual is tested on the device after every solve; the host
+ * reads it every few iterations (as many as the observed contraction predicts
+ * are still needed, at most 32), so the call synchronises a few times.
  *   ux, uy     [nz][ny][nx]   u* on the x face between cells i and i+1 (and
  *                             the y face between j and j+1), periodic
  *   uz         [nz+1][ny][nx] u* on the z face below cell k; the planes 0 and
@@ -211,7 +213,7 @@ psv_status psv_solve_method3(psv_plan* plan, const double* ux, const double* uy,
  * iterations = solves performed, eps of the returned p, eps_start = eps of
  * p = 0 (NaN when p_init is given). MIXED plans run FP32 solves inside the
  * loop, which corrects them. Stops without error at max_iter
- * (info->converged = 0). Synchronises every few iterations. */
+ * (info->converged = 0). Synchronises every few iterations, as Method III does. */
 typedef enum { PSV_ITER_METHOD1 = 1, PSV_ITER_METHOD2 = 2, PSV_ITER_METHOD3 = 3 } psv_iteration;
 psv_status psv_solve_converged(psv_plan* plan, const double* f, const double* rho,
                                int32_t iteration, double eps_t, int32_t max_iter,
