@@ -15,11 +15,12 @@
 //      row kc-1:   aa x_first + x_last + cc x_{first of next chunk} = d_{kc-1}
 //    written back in place;
 //  * interface pass: per pair, the 2 nc rows (first, last) of its nc chunks
-//    form a tridiagonal system with unit diagonal, solved by Thomas with the
-//    factors precomputed per plan (they do not depend on the data); its tile
-//    0 solves the singular (0, 0) pair in FP64: projection of the right-hand
-//    side (removal of its volume-weighted mean), flux integration from the
-//    bottom wall, gauge sum_k h_k x_k = 0;
+//    form a tridiagonal system with unit diagonal, solved with the Thomas
+//    factors precomputed per plan (they do not depend on the data), its two
+//    sweeps as affine scans over up to 8 lanes per pair; its tile 0 solves
+//    the singular (0, 0) pair in FP64: projection of the right-hand side
+//    (removal of its volume-weighted mean), flux integration from the bottom
+//    wall, gauge sum_k h_k x_k = 0;
 //  * inverse y tile: back substitution of the interior rows from x_first and
 //    x_last, then the inverse FFT along y, in place.
 // The elimination coefficients of every row are recomputed where they are
