@@ -107,9 +107,13 @@ def kernel_row(name, rec, spec, kc):
 
 
 def source_digest():
+    """Digest of the device-code sources (.hip, .hpp): counter traffic taken
+    on other kernels is not reported."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2005_11806_amd", "csrc")
     for f in sorted(os.listdir(csrc)):
+        if not f.endswith((".hip", ".hpp")):
+            continue
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(f.encode() + fh.read())
     return h.hexdigest()[:16]
