@@ -30,3 +30,35 @@ def test_autotuned_plan_matches_default(gpu, precision, tmp_path, monkeypatch):
     assert i_tun.relres <= (1e-12 if precision == "fp64" else 1e-10)
     (po,), _ = O.solve(f, g, rho, pp, with_relres=False)
     assert rel_max_err(host(p_tun), po) <= (1e-11 if precision == "fp64" else 1e-8)
+
+
+def test_cache_entries_of_every_format(tmp_path):
+    """Cache lines written with 3, 4 or 5 fields (lines per block, chunk rows,
+    then optionally the inverse pass's lines per block and the stencil
+    choice) are all honoured; a fresh process reads them."""
+    import json
+    import subprocess
+    import sys
+    import torch
+    arch = torch.cuda.get_device_properties(0).gcnArchName
+    cache = tmp_path / "tune.txt"
+    cache.write_text(f"{arch}:32x32x24:fp64:method1 2 4\n"
+                     f"{arch}:48x32x24:fp64:method1 4 8 2\n"
+                     f"{arch}:64x32x24:fp64:method1 8 4 2 0\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    script = (
+        "import json, sys\n"
+        f"sys.path.insert(0, {root!r})\n"
+        "import paper_2005_11806_amd as psv\n"
+        "out = {}\n"
+        "for nx in (32, 48, 64):\n"
+        "    plan = psv.Plan(psv.Grid(nx, 32, 24, 1.0, 1.0, 1.0), autotune=1)\n"
+        "    out[nx] = plan.launch_shape()\n"
+        "print(json.dumps(out))\n")
+    env = dict(os.environ, PSV_AUTOTUNE_CACHE=str(cache))
+    res = subprocess.run([sys.executable, "-c", script], env=env, capture_output=True, text=True,
+                         timeout=240)
+    assert res.returncode == 0, res.stderr[-2000:]
+    shapes = json.loads(res.stdout.strip().splitlines()[-1])
+    say(f"cached shapes {shapes}")
+    assert shapes == {"32": [2, 4], "48": [4, 8], "64": [8, 4]}
