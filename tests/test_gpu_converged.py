@@ -184,3 +184,16 @@ def test_iteration_counts_rising_bubble(gpu):
     assert counts["method3"] < counts["method2"] < counts["method1"]
     for it in ("method1", "method2"):
         assert rel_max_err(ps[it], ps["method3"]) <= 1e-8
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_converged_direct_stencil(gpu, precision):
+    """The converged solve with the forward pass reading its stencil
+    neighbours directly (the choice the autotuner makes at 128^3)."""
+    spec, g, f, rho, _ = _case((32, 24, 20), True, 7)
+    eps_t = 1e-11 * np.abs(f).sum()
+    ref = C.solve(f, rho, g, eps_t, 300)
+    plan = gpu.Plan(gpu.Grid.from_spec(spec), precision=precision, x_stencil="direct")
+    p, info = plan.solve_converged(dev(f), dev(rho), eps_t=eps_t, max_iter=300)
+    assert info.converged and abs(info.iterations - (len(ref.eps) - 1)) <= 2
+    assert rel_max_err(host(p), ref.p) <= 1e-8
