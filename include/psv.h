@@ -256,9 +256,14 @@ psv_status psv_relres(psv_plan* plan, const double* r, const double* p, void* st
                       double* relres);
 
 /* Batched uneven problems (one grid per problem, x/y periodic, z walls) solved
- * together: a persistent-kernel launch over a task queue, replayed from a
- * captured HIP graph after the first call. Pointer arrays are HOST arrays
- * of DEVICE pointers; rho0 is a HOST array (<= 0 selects min(rho)). */
+ * together: per pass, one launch over the tiles of every problem
+ * (opts.batch_executor 0 or 1), or one persistent-kernel launch over a task
+ * queue (2); the launches are captured in a HIP graph on the first call and
+ * replayed after. Pointer arrays are HOST arrays of DEVICE pointers; rho0 is
+ * a HOST array (<= 0 selects min(rho)). Each call copies its pointer table to
+ * the device on `stream` and, before rewriting that table, waits on the host
+ * until the previous call's copy has run. Calls on one batch share its
+ * workspace: the caller orders calls made on different streams. */
 psv_status psv_batch_create(int32_t n, const psv_grid* grids, const psv_opts* opts,
                             psv_batch** out);
 psv_status psv_batch_solve(psv_batch* batch, const double* const* f, const double* const* rho,

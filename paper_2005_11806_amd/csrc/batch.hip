@@ -448,6 +448,10 @@ struct psv_batch {
     psv::ProblemDesc* d_desc = nullptr;
     psv::ProblemIO* d_io = nullptr;
     psv::ProblemIO* h_io = nullptr;  // pinned
+    // the copy of h_io to d_io reads h_io when the stream reaches it: the next
+    // call waits for this event before it rewrites the table
+    hipEvent_t io_copied = nullptr;
+    bool io_pending = false;
     std::vector<psv::PassLaunch> seq[2];  // per graph: without / with the final check
     std::vector<int*> starts[2];
     hipGraph_t graph[2] = {nullptr, nullptr};
@@ -658,6 +662,7 @@ void batch_create(psv_batch& B, int n, const psv_grid* grids, const psv_opts& o)
     PSV_HIP(hipMalloc(&B.d_io, n * sizeof(ProblemIO)));
     PSV_HIP(hipHostMalloc(&B.h_io, n * sizeof(ProblemIO)));
     std::memset(B.h_io, 0, n * sizeof(ProblemIO));
+    PSV_HIP(hipEventCreateWithFlags(&B.io_copied, hipEventDisableTiming));
     PSV_HIP(hipMalloc(&B.d_ticket, 2 * sizeof(int)));
     PSV_HIP(hipHostMalloc(&B.h_err, sizeof(int)));
     *B.h_err = 0;
@@ -684,12 +689,15 @@ void batch_free(psv_batch& B) {
     if (B.d_desc) (void)hipFree(B.d_desc);
     if (B.d_io) (void)hipFree(B.d_io);
     if (B.h_io) (void)hipHostFree(B.h_io);
+    if (B.io_copied) (void)hipEventDestroy(B.io_copied);
 }
 
 // One batched solve: upload the per-call pointer table, then replay the
 // captured graph (captured on first use for this `check` setting).
 void batch_solve(psv_batch& B, hipStream_t s, bool check) {
     PSV_HIP(hipMemcpyAsync(B.d_io, B.h_io, B.n * sizeof(ProblemIO), hipMemcpyHostToDevice, s));
+    PSV_HIP(hipEventRecord(B.io_copied, s));
+    B.io_pending = true;
     const int gi = check ? 1 : 0;
     if (!B.exec[gi]) {
         batch_build(B, check);
@@ -717,6 +725,12 @@ bool batch_fp32(const psv_batch& B) { return B.fp32; }
 
 void batch_set_io(psv_batch& B, int p, const double* f, const double* rho, const double* pprev,
                   double* pout, double rho0, bool want_r) {
+    // the previous call's copy of the table may still be queued behind work
+    // on its stream
+    if (B.io_pending) {
+        PSV_HIP(hipEventSynchronize(B.io_copied));
+        B.io_pending = false;
+    }
     ProblemIO& io = B.h_io[p];
     io.f = f;
     io.rho = rho;

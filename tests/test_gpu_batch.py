@@ -121,3 +121,33 @@ def test_batch64_uneven_mixed(gpu, executor):
         e = rel_max_err(host(outs[i]), po)
         say(f"  problem {i} {g.shape}: vs oracle {e:.2e}")
         assert e <= 1e-8
+
+
+@pytest.mark.parametrize("executor", ["passes", "persistent"])
+def test_calls_queued_back_to_back_keep_their_buffers(gpu, executor):
+    """Two calls queued behind long work on the stream, each with its own
+    inputs and outputs: the second call rewrites the host pointer table only
+    after the first call's copy of it has run, so each call solves its own
+    problems."""
+    ins_a = [oracle_inputs(c) for c in _cases(SMALL[:3], seed0=80)]
+    ins_b = [oracle_inputs(c) for c in _cases(SMALL[:3], seed0=90)]
+    grids = [gpu.Grid.from_spec(c.grid) for c in _cases(SMALL[:3], seed0=80)]
+    b = gpu.Batch(grids, precision="fp64", executor=executor)
+    fa, ra, pa = ([dev(x[j]) for x in ins_a] for j in (1, 2, 3))
+    fb, rb, pb = ([dev(x[j]) for x in ins_b] for j in (1, 2, 3))
+    b.solve(fa, ra, pa)  # captures the graph
+    torch.cuda.synchronize()
+    x = torch.rand(2048, 2048, dtype=torch.float64, device="cuda:0") / 2048
+    y = x
+    for _ in range(8):  # milliseconds of work ahead of the two calls
+        y = y @ x
+    outs_a = b.solve(fa, ra, pa)
+    outs_b = b.solve(fb, rb, pb)
+    torch.cuda.synchronize()
+    assert torch.isfinite(y).all()
+    for ins, outs, tag in ((ins_a, outs_a, "first"), (ins_b, outs_b, "second")):
+        for i, (g, f, rho, pp) in enumerate(ins):
+            (po,), _ = O.solve(f, g, rho, pp, with_relres=False)
+            e = rel_max_err(host(outs[i]), po)
+            say(f"{executor} {tag} call, problem {i}: vs oracle {e:.2e}")
+            assert e <= 1e-11, (tag, i, e)
