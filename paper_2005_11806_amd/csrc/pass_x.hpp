@@ -160,6 +160,14 @@ __device__ __forceinline__ void fwd_x_tile(const XGeom& g, const Stencil& st, co
         double pw, pe, rw, re;
     };
     constexpr int PF = (MODE == FWD_CONST || STAGE) ? 2 : 1;
+    // Without staging, the x neighbours of a pair (cell 2n-1 is the .y of pair
+    // n-1, cell 2n+2 the .x of pair n+1) come from the neighbouring lanes
+    // where a wave holds whole lines (N divides 64: groups of N lanes, wrapping
+    // periodically) or 64 consecutive pairs of one line (64 divides N: only a
+    // wave's first and last lanes load theirs). Pairs map to lanes in order, so
+    // lane exchanges replace two loads per field.
+    constexpr bool XLANE = !STAGE && N > 0 && (64 % N == 0 || N % 64 == 0);
+    constexpr int XG = (N > 0 && N < 64) ? N : 64;  // lanes per exchange group
     const double* pd = a.pprev;
     const double* rd = a.rho;
     const int npair = lb * M;
@@ -198,12 +206,15 @@ __device__ __forceinline__ void fwd_x_tile(const XGeom& g, const Stencil& st, co
                     const size_t cs = c2 - (size_t)((j == 0) ? -(g.ny - 1) * M : M);
                     const size_t xw = 2 * c2 + (n == 0 ? nx - 1 : -1);
                     const size_t xe = 2 * c2 + (n + 1 == M ? 2 - nx : 2);
+                    const int lane = t & 63;
+                    const bool ld_w = !XLANE || (N > 64 && lane == 0);
+                    const bool ld_e = !XLANE || (N > 64 && lane == 63);
                     if (has_p) {
                         q.pc = pg[c2];
                         q.pn = pg[cn];
                         q.ps = pg[cs];
-                        q.pw = pd[xw];
-                        q.pe = pd[xe];
+                        if (ld_w) q.pw = pd[xw];
+                        if (ld_e) q.pe = pd[xe];
                         if (has_t) q.ptz = pg[c2 + plane / 2];
                         if (has_b) q.pbz = pg[c2 - plane / 2];
                     }
@@ -211,8 +222,8 @@ __device__ __forceinline__ void fwd_x_tile(const XGeom& g, const Stencil& st, co
                         q.rc = rg[c2];
                         q.rn = rg[cn];
                         q.rs = rg[cs];
-                        q.rw = rd[xw];
-                        q.re = rd[xe];
+                        if (ld_w) q.rw = rd[xw];
+                        if (ld_e) q.re = rd[xe];
                         if (has_t) q.rtz = rg[c2 + plane / 2];
                         if (has_b) q.rbz = rg[c2 - plane / 2];
                     }
@@ -234,6 +245,21 @@ __device__ __forceinline__ void fwd_x_tile(const XGeom& g, const Stencil& st, co
         }
         __syncthreads();
     }
+    // x neighbours by lane exchange: every lane of a group takes part (whole
+    // groups are active together, as npair is a multiple of XG)
+    auto x_nb = [&](const double2& c, double w_loaded, double e_loaded, double& w, double& e) {
+        if constexpr (XLANE) {
+            const int lane = threadIdx.x & 63;
+            const int g0 = lane & ~(XG - 1), li = lane & (XG - 1);
+            const double wl = __shfl(c.y, g0 + ((li + XG - 1) & (XG - 1)), 64);
+            const double el = __shfl(c.x, g0 + ((li + 1) & (XG - 1)), 64);
+            w = (N > 64 && lane == 0) ? w_loaded : wl;
+            e = (N > 64 && lane == 63) ? e_loaded : el;
+        } else {
+            w = w_loaded;
+            e = e_loaded;
+        }
+    };
     // in-plane neighbours of pair n of a line: from the staged rows or the registers
     auto p_nb = [&](const Pre& q, int line, int n, double2& pc, double2& pn, double2& ps, double& pw,
                     double& pe) {
@@ -248,8 +274,7 @@ __device__ __forceinline__ void fwd_x_tile(const XGeom& g, const Stencil& st, co
             pc = q.pc;
             pn = q.pn;
             ps = q.ps;
-            pw = q.pw;
-            pe = q.pe;
+            x_nb(pc, q.pw, q.pe, pw, pe);
         }
     };
     auto r_nb = [&](const Pre& q, int line, int n, double2& rc, double2& rn, double2& rs, double& rw,
@@ -265,8 +290,7 @@ __device__ __forceinline__ void fwd_x_tile(const XGeom& g, const Stencil& st, co
             rc = q.rc;
             rn = q.rn;
             rs = q.rs;
-            rw = q.rw;
-            re = q.re;
+            x_nb(rc, q.rw, q.re, rw, re);
         }
     };
     for (int t0 = threadIdx.x; t0 < npair; t0 += PF * 256) {
