@@ -7,10 +7,14 @@
 
 namespace psv {
 
+// The events only time launches: recording them without the default
+// system-scope fence keeps them from writing back and invalidating the caches
+// between a kernel and the next, which would slow the next kernel and count in
+// its time. Waiting on them still waits for the work before them.
 hipEvent_t Trace::get() {
     if (next == pool.size()) {
         hipEvent_t e;
-        PSV_HIP(hipEventCreate(&e));
+        PSV_HIP(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
         pool.push_back(e);
     }
     return pool[next++];
