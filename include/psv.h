@@ -272,7 +272,10 @@ psv_status psv_batch_solve(psv_batch* batch, const double* const* f, const doubl
 psv_status psv_batch_destroy(psv_batch* batch);
 
 /* Per-kernel timing (profiling aid): with enable = 1 every kernel the plan
- * launches is bracketed by two hipEvents on its launch stream.
+ * launches is bracketed by two hipEvents on its launch stream, recorded
+ * without a system-scope fence (hipEventDisableSystemFence), so that timing
+ * does not write back and invalidate the caches between kernels. The
+ * timings describe eager calls: enable the trace outside stream capture.
  * psv_trace_summary synchronises on the recorded events, writes a JSON object
  * {"kernel": [launches, total_ms], ...} (NUL-terminated, truncated to `len`)
  * into buf, stores the untruncated length in *needed (may be NULL) and
