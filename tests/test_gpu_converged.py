@@ -86,7 +86,7 @@ def test_converged_mixed_and_warm_start(gpu):
     assert rel_max_err(host(p2), ref.p) == 0.0
 
 
-@pytest.mark.parametrize("iteration", ["method1", "method3"])
+@pytest.mark.parametrize("iteration", ["method1", "method2", "method3"])
 @pytest.mark.parametrize("shape,stretched", [((24, 18, 20), True), ((32, 32, 24), False),
                                              ((64, 1, 40), True)])
 def test_converged_adjoint(gpu, shape, stretched, iteration):
