@@ -581,7 +581,7 @@ def main():
         ingest_pmc(args.ingest_pmc[0], args.ingest_pmc[1], args.workload, args.pmc_command)
         return
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); this build has no "
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): the solver has no "
               "multi-GPU path", file=sys.stderr)
         sys.exit(2)
 
