@@ -9,6 +9,7 @@ coefficient system is gated at relres <= 1e-12 (FP64) and <= 1e-10 (mixed).
 """
 import numpy as np
 import pytest
+import torch
 
 import oracle as O
 import workloads as W
@@ -101,6 +102,40 @@ def test_vd128_ten_step_chain(gpu):
     q = pd.clone()
     plan.solve(fd, rho=rd, p_prev=q, n_steps=10, out=q)
     assert rel_max_err(host(q), ps[9]) <= TOL_FP64
+
+
+def test_vd128_chain_as_benchmarked(gpu):
+    """The 128^3 ten-step chain in the configuration the benchmark times:
+    autotuned launch shapes, captured once in a graph and replayed. Every
+    replay (with eager work and a synchronisation between replays) matches the
+    oracle's tenth iterate element by element."""
+    case = W.vd128()
+    g, f, rho, pp = oracle_inputs(case)
+    ps, _ = O.solve(f, g, rho, pp, n_steps=10, with_relres=False)
+    plan = gpu.Plan(gpu.Grid.from_spec(case.grid), autotune=1)
+    say(f"vd128 graph replay, launch shape {plan.launch_shape()}")
+    fd, rd, pd = dev(f), dev(rho), dev(pp)
+    out = torch.empty_like(fd)
+
+    def step():
+        plan.solve(fd, rho=rd, p_prev=pd, n_steps=10, out=out)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        step()
+    torch.cuda.current_stream().wait_stream(s)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        step()
+    for rep in range(3):
+        out.fill_(float("nan"))
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        err = rel_max_err(host(out), ps[9])
+        say(f"  replay {rep}: err {err:.3e}")
+        assert err <= TOL_FP64
+    del graph
 
 
 @pytest.mark.parametrize("shape", [(64, 64, 128), (96, 48, 64)])
