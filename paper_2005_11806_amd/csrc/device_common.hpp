@@ -352,4 +352,13 @@ __device__ inline double block_sum(double v, double* sh) {
     return s;  // valid on thread 0
 }
 
+// Blocks are dispatched round-robin over the 8 XCDs; remap so that each XCD
+// walks a contiguous range of block indices (of planes and lines), and the
+// neighbouring lines and planes a stencil reads stay in its L2.
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+    const int q = nb >> 3, r = nb & 7;
+    const int x = b & 7, i = b >> 3;
+    return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + i;
+}
+
 }  // namespace psv

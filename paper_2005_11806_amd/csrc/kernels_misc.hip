@@ -383,7 +383,10 @@ __global__ void __launch_bounds__(RB) k_adjoint_faces(Geo g, AdjArgs a) {
     const double2* RH = reinterpret_cast<const double2*>(a.rho);
     const double2* P = reinterpret_cast<const double2*>(a.pp);
     double acc = 0.0;
-    for (unsigned q = blockIdx.x * RB + threadIdx.x; q < npair; q += gridDim.x * RB) {
+    // one block per RB consecutive pairs, each XCD on a contiguous range (the
+    // y and z neighbours of its pairs were loaded into its own L2)
+    const unsigned bx = (unsigned)xcd_remap((int)blockIdx.x, (int)gridDim.x);
+    for (unsigned q = bx * RB + threadIdx.x; q < npair; q += gridDim.x * RB) {
         const unsigned line = q / M;
         const unsigned n = q - line * M;
         const unsigned k = line / ny, j = line - k * ny;
@@ -536,7 +539,11 @@ int grid_blocks(size_t n, int thr) {
 }  // namespace
 
 // up to 4096 blocks (the plan's partials hold at least 8192 values)
-int adjoint_blocks(const Plan& p) { return (int)std::min<size_t>(4096, (p.ncell() / 2 + RB - 1) / RB); }
+// One block per RB pairs of cells, bounded by the partial-sum buffer (one
+// slot per block; past it the blocks stride over the pairs).
+int adjoint_blocks(const Plan& p) {
+    return (int)std::min<size_t>((size_t)p.n_partials, (p.ncell() / 2 + RB - 1) / RB);
+}
 
 void launch_min_reduce(const Plan& p, const double* x, double* out_scalar, int* argmin_out,
                        hipStream_t s) {

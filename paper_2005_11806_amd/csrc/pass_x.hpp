@@ -77,15 +77,6 @@ __device__ __forceinline__ double gflux(double rl, double rr, double pl, double 
     return 2.0 * rcp_nr(rl + rr) * (pr - pl);
 }
 
-// Blocks are dispatched round-robin over the 8 XCDs; remap so that each XCD
-// walks a contiguous range of (plane, tile) indices and the neighbouring
-// lines/planes read by the stencil stay in its L2.
-__device__ __forceinline__ int xcd_remap(int b, int nb) {
-    const int q = nb >> 3, r = nb & 7;
-    const int x = b & 7, i = b >> 3;
-    return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + i;
-}
-
 // 7-point L p at one cell (flux form in z; zero wall flux).
 __device__ __forceinline__ double lap_cell(const double* __restrict__ p, int i, int j, int k,
                                            const XGeom& g, const Stencil& st) {
