@@ -538,7 +538,6 @@ int grid_blocks(size_t n, int thr) {
 
 }  // namespace
 
-// up to 4096 blocks (the plan's partials hold at least 8192 values)
 // One block per RB pairs of cells, bounded by the partial-sum buffer (one
 // slot per block; past it the blocks stride over the pairs).
 int adjoint_blocks(const Plan& p) {

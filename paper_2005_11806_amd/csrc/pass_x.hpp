@@ -143,9 +143,9 @@ __device__ __forceinline__ void fwd_x_tile(const XGeom& g, const Stencil& st, co
     // with STAGE, f (or r_in) and p, rho on the planes k +- 1, issued before
     // the rows j0-1 .. j0+lb of p and rho are staged in LDS for the in-plane
     // neighbours, so the two loads overlap; without, every operand (the pair,
-    // its y and z neighbour pairs and its two x neighbours), where the caches
-    // serve the rows that neighbouring pairs and tiles share. The autotuner
-    // picks the faster of the two per grid.
+    // its y and z neighbour pairs and, unless the neighbouring lanes hold them,
+    // its two x neighbours), where the caches serve the rows that neighbouring
+    // pairs and tiles share. The autotuner picks the faster of the two per grid.
     struct Pre {
         double2 f, pc, pn, ps, ptz, pbz, rc, rn, rs, rtz, rbz;
         double pw, pe, rw, re;
