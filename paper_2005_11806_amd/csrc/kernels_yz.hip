@@ -16,6 +16,45 @@ __global__ void __launch_bounds__(256) k_yz(ZArgs z, Radices rad, c2<T>* __restr
         yz_fwd_tile<T, N, KC>(z, rad, spec, tw_g, blockIdx.x, smem_raw);
 }
 
+// Two-dimensional problems (ny = 1): the y transform is the identity and a y
+// tile would hold a single system, so here one thread takes the chunk of one
+// wavenumber m (consecutive threads, consecutive m: the rows of a plane are
+// read and written whole). Same arithmetic as the tiles: the forward chunk is
+// eliminated in registers (rows past nz read as 0), the inverse one
+// back-substituted in place.
+template <typename T, int KC, bool INV>
+__global__ void __launch_bounds__(256) k_z2d(ZArgs z, c2<T>* __restrict__ spec, const int* done) {
+    if (done && *done) return;
+    const int m = (int)blockIdx.x * 256 + (int)threadIdx.x;
+    if (m == 0 || m >= z.mx) return;  // the (0,0) pair is solved apart
+    const int k0 = (int)blockIdx.y * KC;
+    const int nl = min(KC, z.nz - k0);
+    const int SP = z.mx;  // elements per plane when ny = 1
+    c2<T>* col = spec + (size_t)k0 * SP + m;
+    const double lam = z.lamx[m] + z.lamy[0];
+    if constexpr (INV) {
+        chunk_substitute<T, KC>(z, k0, nl, lam, col, SP);
+    } else {
+        c2<T> v[KC];
+#pragma unroll
+        for (int i = 0; i < KC; ++i) v[i] = i < nl ? col[(size_t)i * SP] : c2<T>{(T)0, (T)0};
+        chunk_eliminate<T, KC>(z, k0, lam, v, 1);
+#pragma unroll
+        for (int i = 0; i < KC; ++i)
+            if (i < nl) col[(size_t)i * SP] = v[i];
+    }
+}
+
+template <typename T, bool INV>
+void z2d_launch(const Plan& p, const ZArgs& z, c2<T>* spec, const int* done, hipStream_t s) {
+    const dim3 grid((p.mx + 255) / 256, (p.nz + p.lp.kc - 1) / p.lp.kc);
+    switch (p.lp.kc) {
+        case 4: hipLaunchKernelGGL((k_z2d<T, 4, INV>), grid, dim3(256), 0, s, z, spec, done); break;
+        case 8: hipLaunchKernelGGL((k_z2d<T, 8, INV>), grid, dim3(256), 0, s, z, spec, done); break;
+        default: hipLaunchKernelGGL((k_z2d<T, 16, INV>), grid, dim3(256), 0, s, z, spec, done); break;
+    }
+}
+
 template <typename T, int QM>
 __global__ void __launch_bounds__(IFC_THREADS) k_ifc(ZArgs z, c2<T>* __restrict__ spec, const int* done) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -74,6 +113,10 @@ void yz_dispatch_kc(const Plan& p, const ZArgs& z, c2<T>* spec, const c2<T>* tw,
 template <typename T, bool INV>
 void yz_dispatch(const Plan& p, const ZArgs& z, c2<T>* spec, const c2<T>* tw, const int* done,
                  hipStream_t s) {
+    if (p.ny == 1) {
+        z2d_launch<T, INV>(p, z, spec, done, s);
+        return;
+    }
     switch (p.ny) {
 #define PSV_CASE(n) case n: yz_dispatch_kc<T, n, INV>(p, z, spec, tw, done, s); break;
         PSV_YZ_SIZES(PSV_CASE)
