@@ -251,6 +251,20 @@ __device__ __forceinline__ void fwd_x_tile(const XGeom& g, const Stencil& st, co
             e = e_loaded;
         }
     };
+    // The west face of pair n is the east face of pair n-1 (same operands in
+    // the same order): with lane exchange it comes from the west lane (the
+    // first lane of a 64-pair segment of a longer line evaluates its own).
+    auto west_face = [&](double fe, auto own) -> double {
+        if constexpr (XLANE) {
+            const int lane = threadIdx.x & 63;
+            const int g0 = lane & ~(XG - 1), li = lane & (XG - 1);
+            const double w = __shfl(fe, g0 + ((li + XG - 1) & (XG - 1)), 64);
+            if constexpr (N > 64) return lane == 0 ? own() : w;
+            return w;
+        } else {
+            return own();
+        }
+    };
     // in-plane neighbours of pair n of a line: from the staged rows or the registers
     auto p_nb = [&](const Pre& q, int line, int n, double2& pc, double2& pn, double2& ps, double& pw,
                     double& pe) {
@@ -309,9 +323,9 @@ __device__ __forceinline__ void fwd_x_tile(const XGeom& g, const Stencil& st, co
                     r_nb(q, line, n, rc, rn, rs, rw, re);
                     const double2 rtz = q.rtz, rbz = q.rbz;
                     // x faces: west of 2n, between the pair, east of 2n+1
-                    const double fw = bflux(rw, rc.x, pw, pc.x, two_r0);
                     const double fm = bflux(rc.x, rc.y, pc.x, pc.y, two_r0);
                     const double fe = bflux(rc.y, re, pc.y, pe, two_r0);
+                    const double fw = west_face(fe, [&] { return bflux(rw, rc.x, pw, pc.x, two_r0); });
                     double d0 = (fm - fw) * idx2, d1 = (fe - fm) * idx2;
                     d0 += (bflux(rc.x, rn.x, pc.x, pn.x, two_r0) - bflux(rs.x, rc.x, ps.x, pc.x, two_r0)) * idy2;
                     d1 += (bflux(rc.y, rn.y, pc.y, pn.y, two_r0) - bflux(rs.y, rc.y, ps.y, pc.y, two_r0)) * idy2;
@@ -330,9 +344,9 @@ __device__ __forceinline__ void fwd_x_tile(const XGeom& g, const Stencil& st, co
                     double rw, re;
                     r_nb(q, line, n, rc, rn, rs, rw, re);
                     const double2 rtz = q.rtz, rbz = q.rbz;
-                    const double fw = gflux(rw, rc.x, pw, pc.x);
                     const double fm = gflux(rc.x, rc.y, pc.x, pc.y);
                     const double fe = gflux(rc.y, re, pc.y, pe);
+                    const double fw = west_face(fe, [&] { return gflux(rw, rc.x, pw, pc.x); });
                     double d0 = (fm - fw) * idx2, d1 = (fe - fm) * idx2;
                     d0 += (gflux(rc.x, rn.x, pc.x, pn.x) - gflux(rs.x, rc.x, ps.x, pc.x)) * idy2;
                     d1 += (gflux(rc.y, rn.y, pc.y, pn.y) - gflux(rs.y, rc.y, ps.y, pc.y)) * idy2;
