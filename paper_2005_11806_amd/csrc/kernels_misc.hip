@@ -386,6 +386,14 @@ __global__ void __launch_bounds__(RB) k_adjoint_faces(Geo g, AdjArgs a) {
     // one block per RB consecutive pairs, each XCD on a contiguous range (the
     // y and z neighbours of its pairs were loaded into its own L2)
     const unsigned bx = (unsigned)xcd_remap((int)blockIdx.x, (int)gridDim.x);
+    // x neighbours from the adjacent lanes where a wave holds whole lines (M
+    // divides 64) or 64 pairs of one line (64 divides M; the wave's first and
+    // last lanes load theirs); whole lane groups are active together
+    const bool xl = (M % 64u) == 0 || (64u % M) == 0;
+    const unsigned XG = M < 64u ? M : 64u;
+    const unsigned lane = threadIdx.x & 63u;
+    const int src_w = (int)((lane & ~(XG - 1)) + ((lane + XG - 1) & (XG - 1)));
+    const int src_e = (int)((lane & ~(XG - 1)) + ((lane + 1) & (XG - 1)));
     for (unsigned q = bx * RB + threadIdx.x; q < npair; q += gridDim.x * RB) {
         const unsigned line = q / M;
         const unsigned n = q - line * M;
@@ -397,8 +405,33 @@ __global__ void __launch_bounds__(RB) k_adjoint_faces(Geo g, AdjArgs a) {
         // x neighbours outside the pair (periodic within the line)
         const unsigned cw = line * nx + (n == 0 ? nx - 1 : 2 * n - 1);
         const unsigned ce = line * nx + (n + 1 == M ? 0 : 2 * n + 2);
-        const double mw = vk * a.x[cw], rw = a.rho[cw], pw = a.pp[cw];
-        const double me = vk * a.x[ce], re = a.rho[ce], pe = a.pp[ce];
+        double xw, rw, pw, xe, re, pe;
+        if (xl) {
+            xw = __shfl(xc.y, src_w, 64);
+            rw = __shfl(rc.y, src_w, 64);
+            pw = __shfl(pc.y, src_w, 64);
+            xe = __shfl(xc.x, src_e, 64);
+            re = __shfl(rc.x, src_e, 64);
+            pe = __shfl(pc.x, src_e, 64);
+            if (M > 64u && lane == 0) {
+                xw = a.x[cw];
+                rw = a.rho[cw];
+                pw = a.pp[cw];
+            }
+            if (M > 64u && lane == 63) {
+                xe = a.x[ce];
+                re = a.rho[ce];
+                pe = a.pp[ce];
+            }
+        } else {
+            xw = a.x[cw];
+            rw = a.rho[cw];
+            pw = a.pp[cw];
+            xe = a.x[ce];
+            re = a.rho[ce];
+            pe = a.pp[ce];
+        }
+        const double mw = vk * xw, me = vk * xe;
         double gr0 = 0.0, gr1 = 0.0, gp0 = 0.0, gp1 = 0.0;
         // x faces: west of 2n (lower cell outside), middle, east of 2n+1
         FaceOut f = adj_face(mw, idx, m0, idx, rw, rc.x, pw, pc.x, idx, rho0);

@@ -20,8 +20,11 @@ def _case(shape, stretched=True, seed=11, spheres=4):
     return spec, g, f, rho, pp, case.w
 
 
+# x lines of 8, 16 and 64 pairs take their x neighbours by lane exchange
+# (16, 32, 128), 12 pairs by loads (24); the 256^3 gradient case covers lines
+# of 128 pairs
 @pytest.mark.parametrize("shape,prec,tol", [((16, 12, 10), "fp64", 1e-10), ((32, 48, 17), "fp64", 1e-10),
-                                            ((24, 24, 20), "mixed", 1e-7)])
+                                            ((24, 24, 20), "mixed", 1e-7), ((128, 6, 5), "fp64", 1e-10)])
 def test_adjoint_matches_oracle_explicit_rho0(gpu, shape, prec, tol):
     spec, g, f, rho, pp, w = _case(shape)
     rho0 = float(rho.min()) * 0.9
