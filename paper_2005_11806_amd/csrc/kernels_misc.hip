@@ -368,7 +368,8 @@ __device__ __forceinline__ FaceOut adj_face(double mul, double ihl, double mur, 
 
 // Face products of the adjoint, one thread per pair of cells (2n, 2n+1) of an
 // x line: 16-byte loads of x, rho and p on the pair and on its y and z
-// neighbour pairs, single loads for the two x neighbours outside the pair.
+// neighbour pairs; the two x neighbours outside the pair come from the
+// adjacent lanes where a wave holds them, else by single loads.
 // The pair's three x faces (west, middle, east), four y faces and up to four z
 // faces are evaluated once each; each cell sums the faces it touches. The
 // d/drho0 partial counts each face once, at the cell on its lower (west,
