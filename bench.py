@@ -1,22 +1,33 @@
 #!/usr/bin/env python3
 """Throughput of the eigenexpansion pressure solve on one MI355X.
 
-Default workload (vd128): 128^3 uniform grid, periodic x/y, walls in z,
-two-phase density (20 smoothed spheres, liquid 1000, gas 1-5) and Method-I
-splitting with rho0 = min(rho) computed on the device, FP64, 10 chained
-solves per step (p_prev <- p). One step = one such 10-solve chain; the
-metric counts grid points times solves per second.
+Default workload (c3_fp64): one Method-I pressure solve per step on the
+256x256x512 grid with tanh-stretched z (alpha 1.5), periodic x/y, walls in z,
+two-phase density (200 smoothed spheres, liquid 1000, gas 1-5), rho0 =
+min(rho) computed on the device, FP64, replayed from a captured HIP graph.
+`value` counts grid points solved per second. The same JSON line carries the
+comparisons the metric asks for, each at relres <= 1e-10 and with its error
+against the FP64 oracle:
 
-    python bench.py [--steps K] [--warmup W] [--workload vd128|mixed_tanh|fp64_tanh|const32]
+* mixed_c3: the same problem with FP32 transforms and tridiagonal sweeps and
+  FP64 residual refinement;
+* batched_c4: 64 uneven problems from {64^3, 96x96x128, 128^3, 128x128x192},
+  solved one plan at a time in FP64, and as one batch (per-pass batched
+  launches or one persistent launch, FP64 or mixed);
+* iterated_128: the converged variable-density solve on 128^3 (Method III
+  weights) where each iteration is an eigenexpansion solve, FP64 against FP32
+  solves inside the same loop.
+
+    python bench.py [--steps K] [--warmup W] [--workload NAME]
 
 Prints one JSON line. Inputs are generated on the host (seeded), copied to
 the device and turned into f (discrete divergence) and rho (mixture rule) by
-the library before timing starts; the timed region holds only solves.
+the library before timing starts; the timed regions hold only solves.
 
-The roofline object describes the kernel with the largest share of GPU time,
-measured with HIP events around each of its launches (psv_trace_*) in an
-eager pass of the same K steps on the launch stream. The CPU baseline is the
-FP64 oracle on a bounded sample of the same workload.
+The roofline object describes the kernel with the largest share of the
+headline solve's GPU time, measured with HIP events around each of its
+launches (psv_trace_*) in an eager pass of the same K steps on the launch
+stream. The CPU baseline is the FP64 oracle on the same grid and inputs.
 """
 from __future__ import annotations
 
@@ -206,6 +217,45 @@ def blas_threads():
         return max(n) if n else 1
     except Exception:
         return os.cpu_count() or 1
+
+
+def host_info():
+    """CPU model, usable cores and the BLAS library numpy runs on."""
+    import numpy  # noqa: F401  (BLAS is only visible once numpy is loaded)
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    blas = None
+    try:
+        from threadpoolctl import threadpool_info
+        for i in threadpool_info():
+            if i.get("user_api") == "blas":
+                blas = {"vendor": i.get("internal_api"), "version": i.get("version"),
+                        "threads": i.get("num_threads")}
+    except Exception:
+        pass
+    ncpu = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return {"cpu_model": model, "nproc": ncpu, "blas": blas}
+
+
+def oracle_solves(f, g, rho, p_prev, budget_s=15.0):
+    """Times the FP64 oracle's Method-I solve of one step on the host: as many
+    solves of the same inputs as fit in about budget_s seconds (at least
+    one). Returns (p of the solve, seconds per solve, solves timed)."""
+    import oracle as O
+    times = []
+    p = None
+    while not times or (sum(times) + times[-1] <= budget_s):
+        t0 = time.perf_counter()
+        (p,), _ = O.solve(f, g, rho, p_prev, n_steps=1, with_relres=False)
+        times.append(time.perf_counter() - t0)
+    return p, sum(times) / len(times), len(times)
 
 
 def cpu_baseline(case, n_steps_target, budget_s=15.0):
@@ -503,7 +553,7 @@ def bench_batch(args):
     dev = torch.device("cuda:0")
     to = lambda a: torch.from_numpy(a).to(dev)  # noqa: E731
     grids = [psv.Grid.from_spec(c.grid) for c in cases]
-    plans = [psv.Plan(g, precision=prec) for g in grids]
+    plans = [psv.Plan(g, precision=prec, autotune=args.autotune) for g in grids]
     fs = [pl.divergence(*(to(u) for u in c.faces)) for pl, c in zip(plans, cases)]
     rs = [pl.density_from_colour(to(c.phi), to(c.rho_gas), c.rho_liq) for pl, c in zip(plans, cases)]
     ps = [to(c.p_prev) for c in cases]
@@ -526,7 +576,7 @@ def bench_batch(args):
             step()
         run = graph.replay
     else:
-        batch = psv.Batch(grids, precision=prec, executor=executor)
+        batch = psv.Batch(grids, precision=prec, executor=executor, autotune=args.autotune)
         _, infos = batch.solve(fs, rs, ps, outs, info=True)
 
         def run():
@@ -558,19 +608,247 @@ def bench_batch(args):
     print(json.dumps(line), flush=True)
 
 
+def _timed(run, steps, warmup):
+    """Seconds per call of run(): warmup untimed calls, then exactly `steps`
+    calls between two device synchronisations."""
+    import torch
+    for _ in range(warmup):
+        run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        run()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def _graphed(step):
+    """step() captured once in a HIP graph (after one eager warm-up call on a
+    side stream); returns the replay function."""
+    import torch
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        step()
+    torch.cuda.current_stream().wait_stream(s)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        step()
+    return graph.replay
+
+
+def _batch_leg(args):
+    """C4: 64 uneven problems, one plan at a time (FP64) against the batched
+    executors, each at its relres, with a sample of problems against the
+    oracle."""
+    import numpy as np
+    import torch
+    import oracle as O
+    import paper_2005_11806_amd as psv
+    import workloads as W
+    cases = W.batch()
+    dev = torch.device("cuda:0")
+    to = lambda a: torch.from_numpy(a).to(dev)  # noqa: E731
+    grids = [psv.Grid.from_spec(c.grid) for c in cases]
+    plans = [psv.Plan(g, precision="fp64", autotune=args.autotune) for g in grids]
+    fs = [pl.divergence(*(to(u) for u in c.faces)) for pl, c in zip(plans, cases)]
+    rs = [pl.density_from_colour(to(c.phi), to(c.rho_gas), c.rho_liq) for pl, c in zip(plans, cases)]
+    ps = [to(c.p_prev) for c in cases]
+    ntot = sum(c.grid.n for c in cases)
+    sizes = np.array([c.grid.n for c in cases])
+    sample = sorted({int(np.argmin(sizes)), int(np.argmax(sizes))})
+    refs = {}
+    for i in sample:
+        g = O.Grid.from_spec(cases[i].grid)
+        f = O.divergence_of_faces(*cases[i].faces, g)
+        rho = O.mixture_density(cases[i].phi, cases[i].rho_gas, cases[i].rho_liq)
+        (refs[i],), _ = O.solve(f, g, rho, cases[i].p_prev, with_relres=False)
+
+    def err(outs):
+        return max(float(np.abs(outs[i].cpu().numpy() - refs[i]).max() / np.abs(refs[i]).max())
+                   for i in sample)
+
+    out = {"workload": "64 problems from {64^3, 96x96x128, 128^3, 128x128x192}, Method I, "
+                       "20 spheres each, rho0 = min rho", "problems": len(cases), "cells": ntot,
+           "oracle_sample": [[cases[i].grid.nx, cases[i].grid.ny, cases[i].grid.nz] for i in sample]}
+    seq_out = [torch.empty_like(f) for f in fs]
+    infos = [pl.solve(f, rho=r, p_prev=p, out=o, info=True)[1]
+             for pl, f, r, p, o in zip(plans, fs, rs, ps, seq_out)]
+
+    def seq_step():
+        for pl, f, r, p, o in zip(plans, fs, rs, ps, seq_out):
+            pl.solve(f, rho=r, p_prev=p, out=o)
+    t = _timed(_graphed(seq_step), args.steps, args.warmup)
+    out["fp64_sequential"] = {"ms": 1e3 * t, "pts_per_s": ntot / t,
+                              "max_relres": max(i.relres for i in infos), "err_vs_oracle": err(seq_out)}
+    t_seq = t
+    for name, prec, ex in (("fp64_batched", "fp64", "default"), ("mixed_batched", "mixed", "default"),
+                           ("mixed_persistent", "mixed", "persistent")):
+        b = psv.Batch(grids, precision=prec, executor=ex, autotune=args.autotune)
+        outs = [torch.empty_like(f) for f in fs]
+        _, binf = b.solve(fs, rs, ps, outs, info=True)
+        t = _timed(lambda: b.solve(fs, rs, ps, outs), args.steps, args.warmup)
+        out[name] = {"ms": 1e3 * t, "pts_per_s": ntot / t, "speedup_vs_fp64_sequential": t_seq / t,
+                     "max_relres": max(i.relres for i in binf),
+                     "refine_steps": sorted(set(i.refine_steps for i in binf)),
+                     "err_vs_oracle": err(outs)}
+        b.close()
+    return out
+
+
+def _iterated_leg(args):
+    """The converged variable-density solve (Method III weights) on 128^3:
+    FP64 solves against FP32 solves inside the same loop, to the same
+    summed residual."""
+    import torch
+    import paper_2005_11806_amd as psv
+    import workloads as W
+    case = W.converged_128()
+    spec = case.grid
+    dev = torch.device("cuda:0")
+    to = lambda a: torch.from_numpy(a).to(dev)  # noqa: E731
+    out = {"workload": "128^3 two-phase (20 spheres, rho_l 10, rho_g 1-5), converged solve "
+                       "D(rho_f^-1 G p) = f iterated with Method III weights to eps <= 1e-10 eps(0)"}
+    for prec in ("fp64", "mixed"):
+        plan = psv.Plan(psv.Grid.from_spec(spec), precision=prec, autotune=args.autotune)
+        f = plan.divergence(*(to(u) for u in case.faces))
+        rho = plan.density_from_colour(to(case.phi), to(case.rho_gas), case.rho_liq)
+        p = torch.empty(spec.nz, spec.ny, spec.nx, dtype=torch.float64, device=dev)
+        _, i0 = plan.solve_converged(f, rho, iteration="method3", max_iter=1, out=p)
+        eps_t = 1e-10 * i0.eps_start
+        _, info = plan.solve_converged(f, rho, iteration="method3", eps_t=eps_t, max_iter=500, out=p)
+        t = _timed(lambda: plan.solve_converged(f, rho, iteration="method3", eps_t=eps_t,
+                                                max_iter=500, out=p), max(1, args.steps // 4), 1)
+        out[prec] = {"ms": 1e3 * t, "pts_per_s": spec.n / t, "iterations": info.iterations,
+                     "eps_over_eps0": info.eps / i0.eps_start}
+    out["mixed_speedup_vs_fp64"] = out["fp64"]["ms"] / out["mixed"]["ms"]
+    return out
+
+
+def bench_headline(args):
+    """The default line: the 256x256x512 FP64 solve, its dominant kernel's
+    roofline, the oracle on the host, and the mixed / batched / iterated
+    comparisons."""
+    import numpy as np
+    import torch
+    import oracle as O
+    import paper_2005_11806_amd as psv
+    import workloads as W
+    case = W.mixed_tanh()
+    spec = case.grid
+    n = spec.n
+    dev = torch.device("cuda:0")
+    to = lambda a: torch.from_numpy(a).to(dev)  # noqa: E731
+    plan = psv.Plan(psv.Grid.from_spec(spec), precision="fp64", autotune=args.autotune)
+    f = plan.divergence(*(to(u) for u in case.faces))
+    rho = plan.density_from_colour(to(case.phi), to(case.rho_gas), case.rho_liq)
+    pp = to(case.p_prev)
+    out = torch.empty(spec.nz, spec.ny, spec.nx, dtype=torch.float64, device=dev)
+
+    def step():
+        plan.solve(f, rho=rho, p_prev=pp, out=out)
+
+    _, info = plan.solve(f, rho=rho, p_prev=pp, out=out, info=True)
+    t = _timed(_graphed(step), args.steps, args.warmup)
+    ms = 1e3 * t
+    p64 = out.cpu().numpy()
+
+    # per-kernel event timing over an eager pass of the same K steps
+    plan.trace(True)
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    summary = plan.trace_summary()
+    plan.trace(False)
+    dom = max(summary, key=lambda k: summary[k][1])
+    launches, total_ms = summary[dom]
+    avg_s = total_ms / launches * 1e-3
+    kc = plan.launch_shape()[1]
+    alg = kernel_bytes(dom, spec.nx, spec.ny, spec.nz, kc)
+    achieved = alg / avg_s / 1e9
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom, "c3_fp64"),
+                "kernel": dom, "avg_launch_us": avg_s * 1e6, "algorithmic_bytes": alg,
+                "chunk_rows": kc,
+                "kernels": {k: kernel_row(k, v, spec, kc) for k, v in
+                            sorted(summary.items(), key=lambda kv: -kv[1][1])}}
+
+    if args.legs == "headline":
+        args.no_cpu_baseline = True
+        tm = float("nan")
+    # mixed precision on the same problem
+    pm = None if args.legs == "headline" else psv.Plan(psv.Grid.from_spec(spec), precision="mixed", autotune=args.autotune)
+    if pm is not None:
+        outm = torch.empty_like(out)
+        _, minfo = pm.solve(f, rho=rho, p_prev=pp, out=outm, info=True)
+        tm = _timed(lambda: pm.solve(f, rho=rho, p_prev=pp, out=outm), args.steps, args.warmup)
+        pmix = outm.cpu().numpy()
+        pm.close()
+
+    # the oracle on the host: the same solve, timed, and the reference for both
+    g = O.Grid.from_spec(spec)
+    fo = O.divergence_of_faces(*case.faces, g)
+    ro = O.mixture_density(case.phi, case.rho_gas, case.rho_liq)
+    cpu = None
+    err64 = errm = None
+    if not args.no_cpu_baseline:
+        po, t_cpu, nsolves = oracle_solves(fo, g, ro, case.p_prev)
+        scale = np.abs(po).max()
+        err64 = float(np.abs(p64 - po).max() / scale)
+        errm = float(np.abs(pmix - po).max() / scale)
+        hi = host_info()
+        cpu = {"value": n / t_cpu, "unit": "grid_pts/s",
+               "cores": (hi["blas"] or {}).get("threads") or hi["nproc"], "kind": "oracle",
+               "sample": f"{nsolves} full Method-I solve(s) of the same 256x256x512 grid and inputs "
+                         f"(matrix-form DFT + textbook Thomas), {t_cpu:.2f} s each",
+               "host": hi}
+
+    comparisons = None if args.legs == "headline" else {
+        "mixed_c3": {"workload": "same grid and inputs, FP32 transforms and tridiagonal sweeps, "
+                                 "FP64 residual refinement to relres 1e-10",
+                     "ms": 1e3 * tm, "pts_per_s": n / tm, "relres": minfo.relres,
+                     "refine_steps": minfo.refine_steps, "err_vs_oracle": errm,
+                     "speedup_vs_fp64": t / tm},
+        "batched_c4": _batch_leg(args),
+        "iterated_128": _iterated_leg(args),
+    }
+    line = {
+        "metric": METRIC, "value": n / t, "unit": "grid_pts/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (seeded generators in workloads/)",
+        "config": {"workload": "c3_fp64: 256x256x512, z tanh-stretched (alpha 1.5), Method I "
+                               "(rho0 = min rho on the device), 200 spheres, rho_l 1000, "
+                               "rho_g 1-5, FP64, one solve per step, graph-replayed",
+                   "grid": [spec.nx, spec.ny, spec.nz], "precision": "fp64",
+                   "relres": info.relres, "err_vs_oracle": err64,
+                   "whole_step": {"algorithmic_bytes": 32 * n,
+                                  "alg_gbs": 32 * n / t / 1e9,
+                                  "frac_of_peak": 32 * n / t / 1e9 / HBM_PEAK_GBS,
+                                  "note": "32 B/pt: f, rho, p_prev in and p out, FP64"},
+                   "comparisons": comparisons},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="vd128",
-                    choices=sorted(WORKLOADS) + sorted(BATCH_WORKLOADS) + sorted(METHOD3_WORKLOADS)
+    ap.add_argument("--workload", default="c3_fp64",
+                    choices=["c3_fp64"] + sorted(WORKLOADS) + sorted(BATCH_WORKLOADS) + sorted(METHOD3_WORKLOADS)
                     + sorted(GRAD_WORKLOADS) + sorted(CONVERGED_WORKLOADS)
                     + sorted(METHODS2D_WORKLOADS))
     ap.add_argument("--mode", default="graph", choices=["graph", "eager"])
-    ap.add_argument("--autotune", type=int, default=1, choices=[0, 1],
-                    help="tune launch shapes at plan creation (outside the timed region)")
+    ap.add_argument("--autotune", type=int, default=2, choices=[0, 1, 2],
+                    help="launch shapes: 0 built-in, 1 from the cache, 2 tuned at plan creation "
+                         "when the cache has none (outside the timed region)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--legs", default="all", choices=["all", "headline"],
+                    help="c3_fp64: 'headline' runs the FP64 solve alone (for counter runs)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first run 3 plain device copies of 256 MiB (counter calibration)")
     ap.add_argument("--ingest-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -588,6 +866,17 @@ def main():
     import torch
     import paper_2005_11806_amd as psv
 
+    if args.copy_probe:
+        a = torch.ones(COPY_PROBE_BYTES // 8, dtype=torch.float64, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    if args.workload == "c3_fp64":
+        bench_headline(args)
+        return
     if args.workload in BATCH_WORKLOADS:
         bench_batch(args)
         return
@@ -603,14 +892,6 @@ def main():
     if args.workload in METHODS2D_WORKLOADS:
         bench_methods2d(args)
         return
-
-    if args.copy_probe:
-        a = torch.ones(COPY_PROBE_BYTES // 8, dtype=torch.float64, device="cuda:0")
-        b = torch.empty_like(a)
-        for _ in range(3):
-            b.copy_(a)
-        torch.cuda.synchronize()
-        del a, b
 
     wl = WORKLOADS[args.workload]
     case = make_case(args.workload)

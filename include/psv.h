@@ -82,11 +82,19 @@ typedef struct {
     double tol;              /* MIXED: target relative residual; <= 0 selects 1e-10 */
     int32_t max_refine;      /* MIXED: maximum refinement sweeps; <= 0 selects 4 */
     int32_t check_inputs;    /* 1: scan inputs for NaN/Inf and rho <= 0 (synchronises) */
-    int32_t autotune;        /* 0: built-in launch shapes; 1: time candidates at plan creation */
+    int32_t autotune;        /* launch shapes (x lines per block, chunk rows, stencil variant):
+                                0 built-in; 1 from the autotune cache when it holds the plan's
+                                (arch, grid, precision, method), else built-in; 2 as 1, but
+                                when the cache has no entry the candidates are timed at plan
+                                creation (on synthetic data, synchronising) and the choice is
+                                added. The cache lives in the process and, when the
+                                environment variable PSV_AUTOTUNE_CACHE names a file, in that
+                                file (read once, appended to). Batches tune each problem's
+                                plan the same way and run every tile in its plan's shape. */
     int32_t batch_executor;  /* batches: 0 default (per-pass launches), 1 per-pass launches,
                                 2 one persistent launch over the task queue */
     int32_t chunk_rows;      /* rows per chunk of the wall-normal partition (planes per y
-                                tile): 0 automatic (tuned when autotune = 1), else 4, 8
+                                tile): 0 automatic (tuned when autotune >= 1), else 4, 8
                                 or 16 (PSV_ERR_UNSUPPORTED_SIZE if its tile does not fit) */
     int32_t x_stencil;       /* neighbours of the forward x pass's stencil: 0 automatic
                                 (staged unless the autotuner finds direct loads faster),
@@ -119,6 +127,21 @@ psv_status psv_plan_workspace_size(const psv_plan* plan, size_t* bytes);
  * solve has 2 ceil(nz / chunk_rows) interface rows per wavenumber pair).
  * Either output pointer may be NULL. */
 psv_status psv_plan_shape(const psv_plan* plan, int* lines_x, int* chunk_rows);
+
+/* Every launch-shape field of a plan. */
+typedef struct {
+    int32_t lines_x;        /* x lines per block of the forward x pass (divides ny) */
+    int32_t lines_x_inv;    /* x lines per block of the inverse x pass (divides ny) */
+    int32_t chunk_rows;     /* rows per chunk of the wall-normal partition: 4, 8 or 16 */
+    int32_t x_staged;       /* forward x pass: 1 stencil rows staged in LDS, 0 loaded directly */
+} psv_shape;
+/* psv_plan_get_shape reads the shape the plan runs with; psv_plan_set_shape
+ * replaces it (host-side checks first: PSV_ERR_INVALID_ARG for a field out of
+ * range, PSV_ERR_UNSUPPORTED_SIZE when a tile does not fit the LDS of a block;
+ * a new chunk_rows recomputes the interface factor table and synchronises the
+ * device). Results do not depend on the shape beyond rounding. */
+psv_status psv_plan_get_shape(const psv_plan* plan, psv_shape* shape);
+psv_status psv_plan_set_shape(psv_plan* plan, const psv_shape* shape);
 psv_status psv_plan_destroy(psv_plan* plan);
 
 /* One or more chained solves (Sec. 3.3.1, Eq. poisson_me1).

@@ -159,6 +159,23 @@ class Plan:
         check(lib().psv_plan_shape(self._h, C.byref(lx), C.byref(kc)))
         return lx.value, kc.value
 
+    def get_shape(self) -> dict:
+        """Every launch-shape field (psv_plan_get_shape)."""
+        sh = _abi.psv_shape()
+        check(lib().psv_plan_get_shape(self._h, C.byref(sh)))
+        return {k: getattr(sh, k) for k, _ in _abi.psv_shape._fields_}
+
+    def set_shape(self, **fields):
+        """Replaces launch-shape fields (psv_plan_set_shape); unnamed ones keep
+        their value."""
+        cur = self.get_shape()
+        unknown = set(fields) - set(cur)
+        if unknown:
+            raise ValueError(f"unknown shape fields {sorted(unknown)}")
+        cur.update(fields)
+        sh = _abi.psv_shape(**{k: int(v) for k, v in cur.items()})
+        check(lib().psv_plan_set_shape(self._h, C.byref(sh)))
+
     def close(self):
         if getattr(self, "_h", None) and self._h.value:
             check(lib().psv_plan_destroy(self._h))
@@ -308,12 +325,14 @@ class Plan:
 
 class Batch:
     """Uneven batch of independent problems solved together (psv_batch_*):
-    one grid per problem, same options for all; replayed from a HIP graph."""
+    one grid per problem, same options for all; replayed from a HIP graph.
+    autotune (0, 1, 2) and x_stencil pick each problem's launch shapes as
+    they do for a Plan."""
 
     _EXEC = {"default": 0, "passes": 1, "persistent": 2}
 
     def __init__(self, grids, precision="mixed", method="method1", tol=1e-10, max_refine=4,
-                 executor="default", chunk_rows=0):
+                 executor="default", chunk_rows=0, autotune=0, x_stencil="auto"):
         self.grids = list(grids)
         n = len(self.grids)
         arr = (_abi.psv_grid * n)()
@@ -330,6 +349,8 @@ class Batch:
         o.max_refine = int(max_refine)
         o.batch_executor = self._EXEC[executor]
         o.chunk_rows = int(chunk_rows)
+        o.autotune = int(autotune)
+        o.x_stencil = _XSTENCIL[x_stencil]
         h = C.c_void_p()
         check(lib().psv_batch_create(n, arr, C.byref(o), C.byref(h)))
         self._h = h

@@ -37,6 +37,11 @@ class psv_info(C.Structure):
                 ("rhs_mean_removed", C.c_double), ("rho0_used", C.c_double)]
 
 
+class psv_shape(C.Structure):
+    _fields_ = [("lines_x", C.c_int32), ("lines_x_inv", C.c_int32), ("chunk_rows", C.c_int32),
+                ("x_staged", C.c_int32)]
+
+
 class psv_m3_info(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("converged", C.c_int32), ("eps", C.c_double),
                 ("eps_start", C.c_double)]
@@ -49,6 +54,8 @@ EXPORTS = {
     "psv_plan_create": (C.c_int, [C.POINTER(psv_grid), C.POINTER(psv_opts), C.POINTER(C.c_void_p)]),
     "psv_plan_workspace_size": (C.c_int, [C.c_void_p, C.POINTER(C.c_size_t)]),
     "psv_plan_shape": (C.c_int, [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+    "psv_plan_get_shape": (C.c_int, [C.c_void_p, C.POINTER(psv_shape)]),
+    "psv_plan_set_shape": (C.c_int, [C.c_void_p, C.POINTER(psv_shape)]),
     "psv_plan_destroy": (C.c_int, [C.c_void_p]),
     "psv_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_void_p, C.c_void_p,
                             C.c_int32, C.c_void_p, C.POINTER(psv_info)]),

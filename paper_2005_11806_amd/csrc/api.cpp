@@ -9,6 +9,7 @@
 #include <string>
 
 #include "internal.hpp"
+#include "pass_x.hpp"
 
 namespace psv {
 void validate_grid(const psv_grid* g);
@@ -204,6 +205,42 @@ psv_status psv_plan_shape(const psv_plan* plan, int* lines_x, int* chunk_rows) {
         need(plan != nullptr, "plan is NULL");
         if (lines_x) *lines_x = plan->p.lp.lbx;
         if (chunk_rows) *chunk_rows = plan->p.lp.kc;
+    });
+}
+
+psv_status psv_plan_get_shape(const psv_plan* plan, psv_shape* shape) {
+    return guarded([&] {
+        need(plan != nullptr && shape != nullptr, "plan and shape must be non-NULL");
+        const psv::Launch& l = plan->p.lp;
+        shape->lines_x = l.lbx;
+        shape->lines_x_inv = l.lbx_inv;
+        shape->chunk_rows = l.kc;
+        shape->x_staged = l.xstage;
+    });
+}
+
+psv_status psv_plan_set_shape(psv_plan* plan, const psv_shape* shape) {
+    return guarded([&] {
+        need(plan != nullptr && shape != nullptr, "plan and shape must be non-NULL");
+        Plan& P = plan->p;
+        const psv_shape& h = *shape;
+        for (int lb : {h.lines_x, h.lines_x_inv})
+            need(lb >= 1 && lb <= 64 && P.ny % lb == 0, "lines per x block must divide ny (1..64)");
+        need(h.chunk_rows == 4 || h.chunk_rows == 8 || h.chunk_rows == 16, "chunk_rows must be 4, 8 or 16");
+        need(h.x_staged == 0 || h.x_staged == 1, "x_staged must be 0 or 1");
+        if (!psv::kc_fits(P, h.chunk_rows))
+            psv::fail(PSV_ERR_UNSUPPORTED_SIZE, "the y tile of chunk_rows planes exceeds the LDS of a block");
+        for (int lb : {h.lines_x, h.lines_x_inv})
+            if (psv::x_lds_max(P.nx, lb) > (size_t)psv::LDS_MAX_BLOCK)
+                psv::fail(PSV_ERR_UNSUPPORTED_SIZE, "an x tile of that many lines exceeds the LDS of a block");
+        psv::Launch l = P.lp;
+        l.lbx = h.lines_x;
+        l.lbx_inv = h.lines_x_inv;
+        l.xstage = h.x_staged;
+        PSV_HIP(hipSetDevice(P.device));
+        if (h.chunk_rows != P.lp.kc) psv::plan_set_kc(P, h.chunk_rows);
+        l.kc = P.lp.kc;
+        P.lp = l;
     });
 }
 

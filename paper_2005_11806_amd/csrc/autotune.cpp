@@ -1,12 +1,15 @@
-// Launch-shape autotuner of a plan: lines per x-block (lbx) and planes per
-// y tile, which are also the rows per chunk of the z partition (kc). Each is
-// timed with hipEvents on synthetic data for every candidate that fits the
-// LDS of a block; the fastest is kept, and the tuned solve must match the
-// default-shape solve (FP64: 1e-10, FP32 spectra: 1e-3 relative in the max
-// norm) or the defaults stay. Choices are cached per (arch, grid, precision,
-// method) in the process and, when PSV_AUTOTUNE_CACHE names a file, on disk
-// (one "key lbx kc lbx_inv xstage" line per entry; the last two may be
-// missing).
+// Launch-shape autotuner of a plan: lines per forward and inverse x block
+// (lbx, lbx_inv), how the forward x pass reaches its stencil neighbours
+// (staged rows or direct loads, xstage) and planes per y tile, which are also
+// the rows per chunk of the z partition (kc). Each is timed with hipEvents on synthetic data for every
+// candidate that fits the LDS of a block; the fastest is kept, and the tuned
+// solve must match the default-shape solve (FP64: 1e-10, FP32 spectra: 1e-3
+// relative in the max norm) or the defaults stay. Choices are cached per
+// (arch, grid, precision, method) in the process and, when PSV_AUTOTUNE_CACHE
+// names a file, on disk (one "key lbx kc lbx_inv xstage" line per entry; the
+// last two may be missing). psv_opts.autotune = 1 only looks the plan up in
+// the cache (built-in shapes when it has no entry); 2 also times the
+// candidates when it has none and adds the choice to the cache.
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -123,7 +126,6 @@ bool fits_x(const Plan& p, int lb) {
     return x_lds_max(p.nx, lb) <= 62 * 1024;
 }
 
-
 }  // namespace
 
 void autotune_plan(Plan& p) {
@@ -137,11 +139,13 @@ void autotune_plan(Plan& p) {
             kc_fits(p, it->second.kc)) {
             p.lp.lbx = it->second.lbx;
             p.lp.lbx_inv = it->second.lbx_inv;
-            p.lp.xstage = it->second.xstage;
+            // a stencil variant fixed by the caller wins over the cached one
+            if (!p.opts.x_stencil) p.lp.xstage = it->second.xstage;
             if (!kc_fixed && it->second.kc != p.lp.kc) plan_set_kc(p, it->second.kc);
             return;
         }
     }
+    if (p.opts.autotune < 2) return;  // cache only: the built-in shapes stay
     const bool fp32 = p.opts.precision == PSV_MIXED;
     const size_t n = p.ncell();
     double* buf = nullptr;

@@ -46,7 +46,8 @@ constexpr int RES_TILE = 2048;   // cells per residual tile
 constexpr int MAX_MIN_TILES = 256;
 
 struct ProblemDesc {
-    XGeom xg;
+    XGeom xg;   // forward x tiles (the plan's lines per block and stencil variant)
+    XGeom xgi;  // inverse x tiles (the plan's own lines per block)
     Stencil st;
     ZArgs z;  // rhs_mean set per kind at run time
     int method, fp32;
@@ -76,7 +77,8 @@ struct ProblemIO {
 inline int kind_tiles(const Plan& p, int kind) {
     switch (kind) {
         case K_MINP: return std::min<int>(MAX_MIN_TILES, (int)((p.ncell() + MIN_TILE - 1) / MIN_TILE));
-        case K_FWD: case K_INV: case K_INVADD: case K_RES: return fwd_x_blocks(p);
+        case K_FWD: case K_RES: return fwd_x_blocks(p);
+        case K_INV: case K_INVADD: return (p.ny / p.lp.lbx_inv) * p.nz;
         case K_Y: case K_YI: return yz_tiles(p);
         case K_Z: case K_Z2: return ifc_tiles(p);
         case K_CHK: return (int)((p.ncell() + RES_TILE - 1) / RES_TILE);
@@ -189,16 +191,35 @@ __device__ void chk_tile(const ProblemDesc& D, const ProblemIO& io, int b, doubl
 // device: one tile of one pass of one problem
 #define PSV_BX_SIZES(X) X(16) X(24) X(32) X(48) X(64) X(96) X(128)
 
-template <typename T, int MODE>
-__device__ __forceinline__ void run_fwd(const ProblemDesc& D, const FwdArgs& a, int b,
-                                        unsigned char* smem, double* red) {
+template <typename T, int MODE, bool STAGE>
+__device__ __forceinline__ void run_fwd_s(const ProblemDesc& D, const FwdArgs& a, int b,
+                                          unsigned char* smem, double* red) {
     const c2<T>* tw = reinterpret_cast<const c2<T>*>(D.twx);
     c2<T>* sp = reinterpret_cast<c2<T>*>(D.spec);
     switch (D.xg.M) {
-#define PSV_CASE(n) case n: fwd_x_tile<T, T, MODE, n>(D.xg, D.st, a, tw, sp, b, smem, red); return;
+#define PSV_CASE(n) case n: fwd_x_tile<T, T, MODE, n, STAGE>(D.xg, D.st, a, tw, sp, b, smem, red); return;
         PSV_BX_SIZES(PSV_CASE)
 #undef PSV_CASE
-        default: fwd_x_tile<T, T, MODE, 0>(D.xg, D.st, a, tw, sp, b, smem, red); return;
+        default: fwd_x_tile<T, T, MODE, 0, STAGE>(D.xg, D.st, a, tw, sp, b, smem, red); return;
+    }
+}
+
+// Forward x tile in the problem's stencil variant: SEL = 1 staged rows, 0
+// direct loads (per-pass kernels, one launch per variant), -1 chosen from the
+// problem's geometry at run time (persistent kernel). The constant-
+// coefficient copy has no stencil and always takes the staged variant.
+template <typename T, int MODE, int SEL>
+__device__ __forceinline__ void run_fwd(const ProblemDesc& D, const FwdArgs& a, int b,
+                                        unsigned char* smem, double* red) {
+    if constexpr (MODE == FWD_CONST || SEL == 1) {
+        run_fwd_s<T, MODE, true>(D, a, b, smem, red);
+    } else if constexpr (SEL == 0) {
+        run_fwd_s<T, MODE, false>(D, a, b, smem, red);
+    } else {
+        if (D.xg.stage)
+            run_fwd_s<T, MODE, true>(D, a, b, smem, red);
+        else
+            run_fwd_s<T, MODE, false>(D, a, b, smem, red);
     }
 }
 
@@ -207,11 +228,11 @@ __device__ __forceinline__ void run_inv(const ProblemDesc& D, double* out, int b
     const c2<T>* tw = reinterpret_cast<const c2<T>*>(D.twx);
     const c2<T>* sp = reinterpret_cast<const c2<T>*>(D.spec);
     const double sc = 2.0 / ((double)D.xg.nx * D.xg.ny);
-    switch (D.xg.M) {
-#define PSV_CASE(n) case n: inv_x_tile<T, T, MODE, n>(D.xg, tw, sp, out, D.st.vol, sc, b, smem); return;
+    switch (D.xgi.M) {
+#define PSV_CASE(n) case n: inv_x_tile<T, T, MODE, n>(D.xgi, tw, sp, out, D.st.vol, sc, b, smem); return;
         PSV_BX_SIZES(PSV_CASE)
 #undef PSV_CASE
-        default: inv_x_tile<T, T, MODE, 0>(D.xg, tw, sp, out, D.st.vol, sc, b, smem); return;
+        default: inv_x_tile<T, T, MODE, 0>(D.xgi, tw, sp, out, D.st.vol, sc, b, smem); return;
     }
 }
 
@@ -247,7 +268,7 @@ __device__ __forceinline__ void run_ifc(const ProblemDesc& D, double* mean_out, 
     ifc_tile<T>(z, reinterpret_cast<c2<T>*>(D.spec), b, smem);
 }
 
-template <typename T, int KIND>
+template <typename T, int KIND, int SEL = -1>
 __device__ __forceinline__ void run_task(const ProblemDesc& D, const ProblemIO& io, int b,
                                          unsigned char* smem, double* red) {
     // The done flag is cleared before the first pass and set only by the norm
@@ -268,10 +289,10 @@ __device__ __forceinline__ void run_task(const ProblemDesc& D, const ProblemIO& 
         a.partials = D.fp32 ? D.partials : nullptr;
         if (D.method == PSV_SPLIT_RHO0) {
             a.mode = FWD_METHOD1;
-            run_fwd<T, FWD_METHOD1>(D, a, b, smem, red);
+            run_fwd<T, FWD_METHOD1, SEL>(D, a, b, smem, red);
         } else {
             a.mode = FWD_CONST;
-            run_fwd<T, FWD_CONST>(D, a, b, smem, red);
+            run_fwd<T, FWD_CONST, SEL>(D, a, b, smem, red);
         }
     } else if constexpr (KIND == K_MEAN) {
         mean_tile(D, red);
@@ -294,7 +315,7 @@ __device__ __forceinline__ void run_task(const ProblemDesc& D, const ProblemIO& 
         a.pprev = io.pout;
         a.mean = D.scal + S_RHS_MEAN;
         a.partials = D.partials;
-        run_fwd<T, FWD_RESID>(D, a, b, smem, red);
+        run_fwd<T, FWD_RESID, SEL>(D, a, b, smem, red);
     } else if constexpr (KIND == K_NRM) {
         nrm_tile(D, D.ntiles[K_RES], red, true);
     } else if constexpr (KIND == K_CHK) {
@@ -305,8 +326,9 @@ __device__ __forceinline__ void run_task(const ProblemDesc& D, const ProblemIO& 
 }
 
 // Per-pass batched kernel: block -> (problem, tile) through start[] (prefix of
-// tile counts, nprob + 1 entries).
-template <typename T, int KIND>
+// tile counts, nprob + 1 entries). SEL: stencil variant of the forward x
+// kinds (problems of the other variant have no tiles in this launch).
+template <typename T, int KIND, int SEL>
 __global__ void __launch_bounds__(256) k_batch_pass(const ProblemDesc* __restrict__ desc,
                                                      const ProblemIO* __restrict__ io,
                                                      const int* __restrict__ start, int nprob) {
@@ -318,7 +340,7 @@ __global__ void __launch_bounds__(256) k_batch_pass(const ProblemDesc* __restric
         const int mid = (lo + hi) >> 1;
         if (start[mid] <= blk) lo = mid; else hi = mid;
     }
-    run_task<T, KIND>(desc[lo], io[lo], blk - start[lo], smem_raw, red);
+    run_task<T, KIND, SEL>(desc[lo], io[lo], blk - start[lo], smem_raw, red);
 }
 
 // Persistent executor. Tasks are int4 {problem, level, tile, tiles of the
@@ -432,6 +454,7 @@ __global__ void k_persist_reset(ProblemDesc* desc, int n, int* counters, int nco
 // host
 struct PassLaunch {
     int kind;
+    int sel;     // forward x kinds: stencil variant of this launch (1 staged, 0 direct)
     int refine;  // refinement tile: skipped when the problem converged
     int nblk;
     size_t lds;
@@ -477,30 +500,35 @@ void plan_free(Plan& p);
 
 static size_t kind_lds(const Plan& p, int kind, bool fp32) {
     const size_t cs = fp32 ? sizeof(float2) : sizeof(double2);
-    XGeom g = make_xgeom(p);
-    g.stage = 1;  // batch tiles stage the stencil rows
     switch (kind) {
-        case K_FWD: case K_RES: return fwd_x_lds(g, cs);
-        case K_INV: case K_INVADD: return inv_x_lds(g, cs);
+        case K_FWD: case K_RES: return fwd_x_lds(make_xgeom(p), cs);
+        case K_INV: case K_INVADD: return inv_x_lds(make_xgeom(p, true), cs);
         case K_Y: case K_YI: return yz_lds(p.ny, p.lp.kc, cs);
         case K_Z: case K_Z2: return ifc_lds(p);
         default: return 0;
     }
 }
 
+template <typename T, int KIND, int SEL>
+static void launch_pass_k(const psv_batch& B, const PassLaunch& L, hipStream_t s) {
+    allow_lds(k_batch_pass<T, KIND, SEL>, L.lds);
+    hipLaunchKernelGGL((k_batch_pass<T, KIND, SEL>), dim3(L.nblk), dim3(256), L.lds, s, B.d_desc,
+                       B.d_io, L.d_start, B.n);
+}
+
 template <typename T>
 static void launch_pass(const psv_batch& B, const PassLaunch& L, hipStream_t s) {
     switch (L.kind) {
-#define PSV_K(k)                                                                             \
-    case k:                                                                                  \
-        allow_lds(k_batch_pass<T, k>, L.lds);                                                \
-        hipLaunchKernelGGL((k_batch_pass<T, k>), dim3(L.nblk), dim3(256), L.lds, s, B.d_desc, \
-                           B.d_io, L.d_start, B.n);                                         \
-        break;
-        PSV_K(K_MINP) PSV_K(K_MINF) PSV_K(K_FWD) PSV_K(K_MEAN) PSV_K(K_Y) PSV_K(K_Z) PSV_K(K_Z2)
-        PSV_K(K_YI) PSV_K(K_INV) PSV_K(K_INVADD) PSV_K(K_RES) PSV_K(K_NRM) PSV_K(K_CHK)
-        PSV_K(K_CHKF)
+#define PSV_K(k) case k: launch_pass_k<T, k, 1>(B, L, s); break;
+        PSV_K(K_MINP) PSV_K(K_MINF) PSV_K(K_MEAN) PSV_K(K_Y) PSV_K(K_Z) PSV_K(K_Z2)
+        PSV_K(K_YI) PSV_K(K_INV) PSV_K(K_INVADD) PSV_K(K_NRM) PSV_K(K_CHK) PSV_K(K_CHKF)
 #undef PSV_K
+        case K_FWD:
+            if (L.sel) launch_pass_k<T, K_FWD, 1>(B, L, s); else launch_pass_k<T, K_FWD, 0>(B, L, s);
+            break;
+        case K_RES:
+            if (L.sel) launch_pass_k<T, K_RES, 1>(B, L, s); else launch_pass_k<T, K_RES, 0>(B, L, s);
+            break;
     }
     PSV_HIP(hipGetLastError());
 }
@@ -535,22 +563,31 @@ void batch_build(psv_batch& B, bool check) {
     const std::vector<int> kinds = batch_sequence(B.fp32, B.opts.method, rounds, check);
     B.seq[gi].clear();
     for (int kind : kinds) {
-        PassLaunch L{};
-        L.kind = kind;
-        std::vector<int> st(B.n + 1, 0);
-        size_t lds = 0;
-        for (int p = 0; p < B.n; ++p) {
-            st[p + 1] = st[p] + kind_tiles(*B.plans[p], kind);
-            lds = std::max(lds, kind_lds(*B.plans[p], kind, B.fp32));
+        // the forward x kinds of a Method-I batch run as one launch per
+        // stencil variant, each over the problems whose plan takes it
+        const bool split = (kind == K_FWD && B.opts.method == PSV_SPLIT_RHO0) || kind == K_RES;
+        for (int sel : {1, 0}) {
+            if (!split && sel == 0) continue;
+            PassLaunch L{};
+            L.kind = kind;
+            L.sel = sel;
+            std::vector<int> st(B.n + 1, 0);
+            size_t lds = 0;
+            for (int p = 0; p < B.n; ++p) {
+                const bool mine = !split || B.plans[p]->lp.xstage == sel;
+                st[p + 1] = st[p] + (mine ? kind_tiles(*B.plans[p], kind) : 0);
+                if (mine) lds = std::max(lds, kind_lds(*B.plans[p], kind, B.fp32));
+            }
+            if (st[B.n] == 0) continue;
+            L.nblk = st[B.n];
+            L.lds = lds;
+            int* d = nullptr;
+            PSV_HIP(hipMalloc(&d, st.size() * sizeof(int)));
+            PSV_HIP(hipMemcpy(d, st.data(), st.size() * sizeof(int), hipMemcpyHostToDevice));
+            B.starts[gi].push_back(d);
+            L.d_start = d;
+            B.seq[gi].push_back(L);
         }
-        L.nblk = st[B.n];
-        L.lds = lds;
-        int* d = nullptr;
-        PSV_HIP(hipMalloc(&d, st.size() * sizeof(int)));
-        PSV_HIP(hipMemcpy(d, st.data(), st.size() * sizeof(int), hipMemcpyHostToDevice));
-        B.starts[gi].push_back(d);
-        L.d_start = d;
-        B.seq[gi].push_back(L);
     }
     // persistent queue: level by level, problems largest first (LPT)
     std::vector<int> order(B.n);
@@ -637,7 +674,7 @@ void batch_create(psv_batch& B, int n, const psv_grid* grids, const psv_opts& o)
         ProblemDesc& D = desc[p];
         std::memset(&D, 0, sizeof(D));
         D.xg = make_xgeom(*pl);
-        D.xg.stage = 1;
+        D.xgi = make_xgeom(*pl, true);
         D.st = Stencil{pl->t.inv_h, pl->t.inv_g, pl->t.vol};
         D.z = make_zargs(*pl, pl->scal + S_RHS_MEAN);
         D.method = o.method;

@@ -163,6 +163,24 @@ struct Plan {
 // Builds host tables and uploads them; allocates workspace when alloc_ws.
 void plan_init(Plan& p, const psv_grid& g, const psv_opts& o, bool alloc_ws);
 void plan_free(Plan& p);
+// Sizes, spacings and radix sequences of a plan (no device access).
+void plan_geometry(Plan& p, const psv_grid& g, const psv_opts& o);
+// Built-in launch shapes on the current device (sets p.device and p.lp
+// except kc, which it returns).
+int builtin_shape(Plan& p);
+
+// Table entries, one at a time (the plan and the plan-free solve evaluate
+// the same expressions): FFT twiddle exp(-2 pi i t / n), eigenvalue
+// -4 sin^2(pi m / n) / d^2 of the periodic second difference, z face k, and
+// the z geometry and wall-normal operator at index k (g and inv_g are face
+// arrays of nz + 1 entries; the other fields are zero at k = nz).
+void twiddle(int t, int n, double* re, double* im);
+double periodic_eigenvalue(int m, int n, double d);
+double grid_face(const psv_grid& g, int k);
+struct ZCoef {
+    double h, g, a, b, c, inv_h, inv_g, vol, inv_vol;
+};
+ZCoef z_coef(const psv_grid& g, int k, double dx, double dy);
 
 // ---- launchers (kernels in *.hip) ----
 struct FwdArgs {
@@ -190,6 +208,10 @@ void launch_z_solve(const Plan& p, bool fp32, double* mean_out, const int* done,
 // the interface factor table, synchronising).
 bool kc_fits(const Plan& p, int kc);
 void plan_set_kc(Plan& p, int kc);
+// Bytes of the interface factor table at chunk rows kc, and the kernel that
+// fills p.ifc_tab for p.lp.kc on stream s.
+size_t ifc_table_bytes(const Plan& p, int kc);
+void launch_ifc_table(const Plan& p, hipStream_t s);
 void launch_inv_x(const Plan& p, bool fp32, int mode, double* out, double scale_all,
                   const int* done, hipStream_t s);
 
@@ -201,6 +223,7 @@ void launch_min_reduce(const Plan& p, const double* x, double* out_scalar, int* 
 void launch_norm_finalize(const Plan& p, int nblocks, double tol, hipStream_t s);
 void launch_residual(const Plan& p, const double* r, const double* p_sol, const double* mean,
                      hipStream_t s);
+// Blocks of the forward x pass (also the number of per-block partial sums it writes).
 int fwd_x_blocks(const Plan& p);
 void launch_set_scalar(double* dst, double v, hipStream_t s);
 void launch_density(const Plan& p, const double* phi, const double* rg, double rl, double* out,

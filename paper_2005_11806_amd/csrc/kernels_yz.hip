@@ -174,12 +174,32 @@ bool kc_fits(const Plan& p, int kc) {
     return yz_lds(p.ny, kc, csz) <= (size_t)LDS_MAX_BLOCK;
 }
 
+size_t ifc_table_bytes(const Plan& p, int kc) {
+    const size_t esz = p.opts.precision == PSV_MIXED ? sizeof(float) : sizeof(double);
+    const int nc = (p.nz + kc - 1) / kc;
+    return (size_t)3 * 2 * nc * p.mx * p.ny * esz;
+}
+
+void launch_ifc_table(const Plan& p, hipStream_t s) {
+    const bool fp32 = p.opts.precision == PSV_MIXED;
+    const ZArgs z = make_zargs(p, nullptr);
+    const int nblk = (p.mx * p.ny + TAB_THREADS - 1) / TAB_THREADS;
+    const size_t lds = (size_t)p.lp.kc * TAB_THREADS * (fp32 ? sizeof(float2) : sizeof(double2));
+    if (fp32) {
+        allow_lds(k_ifc_table<float>, lds);
+        hipLaunchKernelGGL(k_ifc_table<float>, dim3(nblk), dim3(TAB_THREADS), lds, s, z,
+                           (float*)p.ifc_tab);
+    } else {
+        allow_lds(k_ifc_table<double>, lds);
+        hipLaunchKernelGGL(k_ifc_table<double>, dim3(nblk), dim3(TAB_THREADS), lds, s, z,
+                           (double*)p.ifc_tab);
+    }
+    PSV_HIP(hipGetLastError());
+}
+
 void plan_set_kc(Plan& p, int kc) {
     if (!kc_fits(p, kc)) fail(PSV_ERR_UNSUPPORTED_SIZE, "chunk rows do not fit the LDS of a block");
-    const bool fp32 = p.opts.precision == PSV_MIXED;
-    const size_t esz = fp32 ? sizeof(float) : sizeof(double);
-    const int nc = (p.nz + kc - 1) / kc;
-    const size_t bytes = (size_t)3 * 2 * nc * p.mx * p.ny * esz;
+    const size_t bytes = ifc_table_bytes(p, kc);
     if (bytes > p.ifc_tab_bytes) {
         if (p.ifc_tab) PSV_HIP(hipFree(p.ifc_tab));
         p.ifc_tab = nullptr;
@@ -188,19 +208,7 @@ void plan_set_kc(Plan& p, int kc) {
         p.ifc_tab_bytes = bytes;
     }
     p.lp.kc = kc;
-    const ZArgs z = make_zargs(p, nullptr);
-    const int nblk = (p.mx * p.ny + TAB_THREADS - 1) / TAB_THREADS;
-    const size_t lds = (size_t)kc * TAB_THREADS * (fp32 ? sizeof(float2) : sizeof(double2));
-    if (fp32) {
-        allow_lds(k_ifc_table<float>, lds);
-        hipLaunchKernelGGL(k_ifc_table<float>, dim3(nblk), dim3(TAB_THREADS), lds, nullptr, z,
-                           (float*)p.ifc_tab);
-    } else {
-        allow_lds(k_ifc_table<double>, lds);
-        hipLaunchKernelGGL(k_ifc_table<double>, dim3(nblk), dim3(TAB_THREADS), lds, nullptr, z,
-                           (double*)p.ifc_tab);
-    }
-    PSV_HIP(hipGetLastError());
+    launch_ifc_table(p, nullptr);
     PSV_HIP(hipDeviceSynchronize());
 }
 

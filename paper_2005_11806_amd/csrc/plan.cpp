@@ -95,25 +95,61 @@ void default_opts(psv_opts* o) {
     o->x_stencil = 0;
 }
 
-// exp(-2 pi i t / n), t = 0..n-1, from the angle reduced to the first octant
-// in extended precision.
-static void twiddles(int n, std::vector<double>& re, std::vector<double>& im) {
-    re.resize(n);
-    im.resize(n);
+// ---- per-element tables: plan_init and the plan-free solve evaluate the
+// same expressions, so both hold the same bits.
+
+// exp(-2 pi i t / n): cosl/sinl of the angle in extended precision, rounded
+// to double, with exact values on the four axes.
+void twiddle(int t, int n, double* re, double* im) {
+    if ((4 * t) % n == 0) {
+        const int q = (4 * t) / n;
+        *re = (q == 0) ? 1.0 : (q == 2 ? -1.0 : 0.0);
+        *im = (q == 1) ? -1.0 : (q == 3 ? 1.0 : 0.0);
+        return;
+    }
     const long double two_pi = 6.283185307179586476925286766559005768L;
-    for (int t = 0; t < n; ++t) {
-        const long double a = two_pi * (long double)t / (long double)n;
-        re[t] = (double)cosl(a);
-        im[t] = (double)-sinl(a);
+    const long double a = two_pi * (long double)t / (long double)n;
+    *re = (double)cosl(a);
+    *im = (double)-sinl(a);
+}
+
+// eigenvalue of the periodic second difference: -4 sin^2(pi m / n) / d^2
+double periodic_eigenvalue(int m, int n, double d) {
+    const long double pi_l = 3.141592653589793238462643383279502884L;
+    const long double s = sinl(pi_l * m / n);
+    return (double)(-4.0L * s * s / ((long double)d * d));
+}
+
+// z face k (0 .. nz): the caller's positions, or uniform spacing lz / nz
+double grid_face(const psv_grid& g, int k) {
+    if (k <= 0) return 0.0;
+    if (k >= g.nz) return g.lz;
+    return g.zf ? g.zf[k] : g.lz * (double)k / g.nz;
+}
+
+static double cell_centre(const psv_grid& g, int k) {
+    return 0.5 * (grid_face(g, k) + grid_face(g, k + 1));
+}
+
+// z geometry and wall-normal operator at index k (cell k for k < nz; the
+// face arrays g and inv_g run to k = nz): a_k x_{k-1} + b_k x_k + c_k x_{k+1}
+// is the flux-form second difference with zero flux through both walls.
+ZCoef z_coef(const psv_grid& g, int k, double dx, double dy) {
+    ZCoef z{};
+    const int nz = g.nz;
+    if (k >= 1 && k <= nz - 1) {
+        z.g = cell_centre(g, k) - cell_centre(g, k - 1);
+        z.inv_g = 1.0 / z.g;
     }
-    // exact values on the axes
-    for (int t = 0; t < n; ++t) {
-        if ((4 * t) % n == 0) {
-            const int q = (4 * t) / n;
-            re[t] = (q == 0) ? 1.0 : (q == 2 ? -1.0 : 0.0);
-            im[t] = (q == 1) ? -1.0 : (q == 3 ? 1.0 : 0.0);
-        }
-    }
+    if (k >= nz) return z;
+    z.h = grid_face(g, k + 1) - grid_face(g, k);
+    if (k > 0) z.a = 1.0 / (z.h * z.g);
+    if (k + 1 < nz) z.c = 1.0 / (z.h * (cell_centre(g, k + 1) - cell_centre(g, k)));
+    z.b = -(z.a + z.c);
+    z.inv_h = 1.0 / z.h;
+    z.vol = dx * dy * z.h;
+    z.inv_vol = 1.0 / z.vol;
+    return z;
 }
 
 template <typename T>
@@ -124,8 +160,9 @@ static T* upload(const std::vector<T>& v) {
     return d;
 }
 
-void plan_init(Plan& p, const psv_grid& g, const psv_opts& o, bool alloc_ws) {
+void plan_geometry(Plan& p, const psv_grid& g, const psv_opts& o) {
     p.grid = g;
+    p.grid.zf = nullptr;  // the caller's array is not retained
     p.opts = o;
     if (p.opts.tol <= 0.0) p.opts.tol = 1e-10;
     if (p.opts.max_refine <= 0) p.opts.max_refine = 4;
@@ -135,61 +172,18 @@ void plan_init(Plan& p, const psv_grid& g, const psv_opts& o, bool alloc_ws) {
     p.mx = g.nx / 2 + 1;
     p.dx = g.lx / g.nx;
     p.dy = g.ly / g.ny;
-    const int nz = g.nz;
-    p.zf.resize(nz + 1);
-    for (int k = 0; k <= nz; ++k) p.zf[k] = g.zf ? g.zf[k] : g.lz * (double)k / nz;
-    p.zf[0] = 0.0;
-    p.zf[nz] = g.lz;
-    p.grid.zf = nullptr;  // the caller's array is not retained
-    p.h.resize(nz);
-    p.zcen.resize(nz);
-    p.g.assign(nz + 1, 0.0);
-    for (int k = 0; k < nz; ++k) {
-        p.h[k] = p.zf[k + 1] - p.zf[k];
-        p.zcen[k] = 0.5 * (p.zf[k] + p.zf[k + 1]);
-    }
-    for (int k = 1; k < nz; ++k) p.g[k] = p.zcen[k] - p.zcen[k - 1];
-    // wall-normal operator: a_k x_{k-1} + b_k x_k + c_k x_{k+1}
-    std::vector<double> a(nz, 0.0), b(nz, 0.0), c(nz, 0.0), inv_h(nz), inv_g(nz + 1, 0.0), vol(nz),
-        inv_vol(nz);
-    for (int k = 0; k < nz; ++k) {
-        if (k > 0) a[k] = 1.0 / (p.h[k] * p.g[k]);
-        if (k + 1 < nz) c[k] = 1.0 / (p.h[k] * p.g[k + 1]);
-        b[k] = -(a[k] + c[k]);
-        inv_h[k] = 1.0 / p.h[k];
-        vol[k] = p.dx * p.dy * p.h[k];
-        inv_vol[k] = 1.0 / vol[k];
-    }
-    for (int k = 1; k < nz; ++k) inv_g[k] = 1.0 / p.g[k];
-    // eigenvalues of the periodic second differences, -4 sin^2(pi m / n) / d^2
-    std::vector<double> lamx(p.mx), lamy(p.ny);
-    const long double pi_l = 3.141592653589793238462643383279502884L;
-    for (int m = 0; m < p.mx; ++m) {
-        const long double s = sinl(pi_l * m / p.nx);
-        lamx[m] = (double)(-4.0L * s * s / ((long double)p.dx * p.dx));
-    }
-    for (int n = 0; n < p.ny; ++n) {
-        const long double s = sinl(pi_l * n / p.ny);
-        lamy[n] = (double)(-4.0L * s * s / ((long double)p.dy * p.dy));
-    }
-    std::vector<double> re, im;
-    std::vector<double2> tx64(p.nx), ty64(p.ny);
-    std::vector<float2> tx32(p.nx), ty32(p.ny);
-    twiddles(p.nx, re, im);
-    for (int t = 0; t < p.nx; ++t) {
-        tx64[t] = double2{re[t], im[t]};
-        tx32[t] = float2{(float)re[t], (float)im[t]};
-    }
-    twiddles(p.ny, re, im);
-    for (int t = 0; t < p.ny; ++t) {
-        ty64[t] = double2{re[t], im[t]};
-        ty32[t] = float2{(float)re[t], (float)im[t]};
-    }
     p.rad_xh = make_radices(p.nx / 2);
     p.rad_y = make_radices(p.ny);
+}
+
+// Built-in launch shapes of the current device: x lines per block bounded by
+// the LDS a block may take (FP64 worst case, leaving 2 KiB for static shared
+// arrays), the caller's stencil variant, and the chunk rows of the z
+// partition (returned, not yet set): the largest of 16, 8, 4 whose y tile
+// takes at most 48 KiB of LDS (three blocks per CU), else the largest that
+// fits a block at all.
+int builtin_shape(Plan& p) {
     PSV_HIP(hipGetDevice(&p.device));
-    // launch shapes: lines per block bounded by the LDS a block may take (FP64
-    // worst case), leaving 2 KiB for static shared arrays
     int lds_max = 0;
     PSV_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, p.device));
     const size_t budget = (size_t)std::min(lds_max, 64 * 1024) - 2048;
@@ -201,9 +195,6 @@ void plan_init(Plan& p, const psv_grid& g, const psv_opts& o, bool alloc_ws) {
         fail(PSV_ERR_UNSUPPORTED_SIZE, "line length exceeds the LDS budget");
     p.lp.lbx_inv = p.lp.lbx;
     p.lp.xstage = p.opts.x_stencil == 2 ? 0 : 1;
-    // chunk rows of the z partition: the largest of 16, 8, 4 whose y tile
-    // takes at most 48 KiB of LDS (three blocks per CU), else the largest
-    // that fits a block at all
     const size_t csz = p.opts.precision == PSV_MIXED ? sizeof(float2) : sizeof(double2);
     int kc = p.opts.chunk_rows;
     if (kc && !kc_fits(p, kc))
@@ -214,7 +205,46 @@ void plan_init(Plan& p, const psv_grid& g, const psv_opts& o, bool alloc_ws) {
         for (int c : {16, 8, 4})
             if (!kc && kc_fits(p, c)) kc = c;
     if (!kc) fail(PSV_ERR_UNSUPPORTED_SIZE, "y lines exceed the LDS of a block");
+    return kc;
+}
 
+void plan_init(Plan& p, const psv_grid& g, const psv_opts& o, bool alloc_ws) {
+    plan_geometry(p, g, o);
+    const int nz = g.nz;
+    p.zf.resize(nz + 1);
+    for (int k = 0; k <= nz; ++k) p.zf[k] = grid_face(g, k);
+    p.h.resize(nz);
+    p.zcen.resize(nz);
+    p.g.assign(nz + 1, 0.0);
+    std::vector<double> a(nz), b(nz), c(nz), inv_h(nz), inv_g(nz + 1), vol(nz), inv_vol(nz);
+    for (int k = 0; k <= nz; ++k) {
+        const ZCoef z = z_coef(g, k, p.dx, p.dy);
+        p.g[k] = z.g;
+        inv_g[k] = z.inv_g;
+        if (k == nz) break;
+        p.h[k] = z.h;
+        p.zcen[k] = cell_centre(g, k);
+        a[k] = z.a;
+        b[k] = z.b;
+        c[k] = z.c;
+        inv_h[k] = z.inv_h;
+        vol[k] = z.vol;
+        inv_vol[k] = z.inv_vol;
+    }
+    std::vector<double> lamx(p.mx), lamy(p.ny);
+    for (int m = 0; m < p.mx; ++m) lamx[m] = periodic_eigenvalue(m, p.nx, p.dx);
+    for (int n = 0; n < p.ny; ++n) lamy[n] = periodic_eigenvalue(n, p.ny, p.dy);
+    std::vector<double2> tx64(p.nx), ty64(p.ny);
+    std::vector<float2> tx32(p.nx), ty32(p.ny);
+    for (int t = 0; t < p.nx; ++t) {
+        twiddle(t, p.nx, &tx64[t].x, &tx64[t].y);
+        tx32[t] = float2{(float)tx64[t].x, (float)tx64[t].y};
+    }
+    for (int t = 0; t < p.ny; ++t) {
+        twiddle(t, p.ny, &ty64[t].x, &ty64[t].y);
+        ty32[t] = float2{(float)ty64[t].x, (float)ty64[t].y};
+    }
+    const int kc = builtin_shape(p);
     p.t.twx64 = upload(tx64);
     p.t.twx32 = upload(tx32);
     p.t.twy64 = upload(ty64);

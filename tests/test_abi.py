@@ -95,6 +95,11 @@ def test_plan_create_rejects_before_device_work():
     o.x_stencil = 3  # only 0, 1 or 2
     assert lib.psv_plan_create(C.byref(g2), C.byref(o), C.byref(h)) == _abi.PSV_ERR_INVALID_ARG
     assert b"x_stencil" in lib.psv_last_error_message()
+    for bad in (-1, 3):
+        lib.psv_opts_default(C.byref(o))
+        o.autotune = bad  # 0 built-in, 1 cache only, 2 tune
+        assert lib.psv_plan_create(C.byref(g2), C.byref(o), C.byref(h)) == _abi.PSV_ERR_INVALID_ARG
+        assert b"autotune" in lib.psv_last_error_message()
     assert lib.psv_plan_create(C.byref(g2), None, None) == _abi.PSV_ERR_INVALID_ARG
     assert lib.psv_plan_shape(None, None, None) == _abi.PSV_ERR_INVALID_ARG
 

@@ -21,7 +21,7 @@ def test_autotuned_plan_matches_default(gpu, precision, tmp_path, monkeypatch):
     g, f, rho, pp = oracle_inputs(case)
     gm = gpu.Grid.from_spec(spec)
     p_def, i_def = gpu.Plan(gm, precision=precision).solve(dev(f), rho=dev(rho), p_prev=dev(pp), info=True)
-    p_tun, i_tun = gpu.Plan(gm, precision=precision, autotune=1).solve(dev(f), rho=dev(rho),
+    p_tun, i_tun = gpu.Plan(gm, precision=precision, autotune=2).solve(dev(f), rho=dev(rho),
                                                                         p_prev=dev(pp), info=True)
     e = rel_max_err(host(p_tun), host(p_def))
     lines = cache.read_text().strip().splitlines() if cache.exists() else []
@@ -62,3 +62,42 @@ def test_cache_entries_of_every_format(tmp_path):
     shapes = json.loads(res.stdout.strip().splitlines()[-1])
     say(f"cached shapes {shapes}")
     assert shapes == {"32": [2, 4], "48": [4, 8], "64": [8, 4]}
+
+
+def test_cache_only_mode_never_times(gpu, tmp_path, monkeypatch):
+    """autotune = 1 looks the plan up in the cache and otherwise keeps the
+    built-in shapes without timing anything (no cache entry appears);
+    autotune = 2 tunes and adds the entry, which a later autotune = 1 plan of
+    the same key then uses."""
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("PSV_AUTOTUNE_CACHE", str(cache))
+    gm = gpu.Grid(64, 48, 36, 1.0, 1.0, 36 / 64)
+    base = gpu.Plan(gm, autotune=0).launch_shape()
+    only = gpu.Plan(gm, autotune=1).launch_shape()
+    assert only == base
+    assert not cache.exists() or cache.read_text().strip() == ""
+    tuned = gpu.Plan(gm, autotune=2).launch_shape()
+    lines = cache.read_text().strip().splitlines()
+    say(f"built-in {base}, tuned {tuned}, cache {lines}")
+    assert len(lines) == 1 and ":64x48x36:fp64:method1 " in lines[0]
+    assert gpu.Plan(gm, autotune=1).launch_shape() == tuned
+
+
+def test_shape_api_round_trip_and_checks(gpu):
+    """psv_plan_get_shape / psv_plan_set_shape: every field round-trips, a
+    shape set by hand solves like the built-in one, bad fields are rejected
+    and leave the plan as it was."""
+    spec = W.GridSpec(64, 32, 16, 1.0, 1.0, 0.5, W.tanh_faces(16, 0.5, 1.5))
+    case = W.two_phase_case("shape", spec, 1, 78, n_spheres=3)
+    g, f, rho, pp = oracle_inputs(case)
+    plan = gpu.Plan(gpu.Grid.from_spec(spec))
+    ref = host(plan.solve(dev(f), rho=dev(rho), p_prev=dev(pp)))
+    plan.set_shape(lines_x=8, lines_x_inv=4, chunk_rows=4, x_staged=0)
+    assert plan.get_shape() == {"lines_x": 8, "lines_x_inv": 4, "chunk_rows": 4, "x_staged": 0}
+    assert plan.launch_shape() == (8, 4)
+    p = host(plan.solve(dev(f), rho=dev(rho), p_prev=dev(pp)))
+    assert rel_max_err(p, ref) <= 1e-12
+    for bad in ({"lines_x": 3}, {"lines_x_inv": 0}, {"chunk_rows": 5}, {"x_staged": 2}):
+        with pytest.raises(gpu.PsvError):
+            plan.set_shape(**bad)
+    assert plan.get_shape()["lines_x"] == 8  # a rejected call changes nothing

@@ -151,3 +151,66 @@ def test_calls_queued_back_to_back_keep_their_buffers(gpu, executor):
             e = rel_max_err(host(outs[i]), po)
             say(f"{executor} {tag} call, problem {i}: vs oracle {e:.2e}")
             assert e <= 1e-11, (tag, i, e)
+
+
+@pytest.mark.parametrize("x_stencil", ["staged", "direct"])
+def test_small_batch_each_stencil_variant(gpu, x_stencil):
+    """Every problem's forward x tiles in the given stencil variant (the batch
+    launches one pass per variant in use), FP64 and mixed, against the
+    oracle."""
+    cases = _cases(SMALL, seed0=110)
+    ins = [oracle_inputs(c) for c in cases]
+    grids = [gpu.Grid.from_spec(c.grid) for c in cases]
+    for precision, tol in (("fp64", 1e-11), ("mixed", 1e-8)):
+        b = gpu.Batch(grids, precision=precision, x_stencil=x_stencil)
+        outs, infos = b.solve([dev(x[1]) for x in ins], [dev(x[2]) for x in ins],
+                              [dev(x[3]) for x in ins], info=True)
+        for i, (g, f, rho, pp) in enumerate(ins):
+            (po,), _ = O.solve(f, g, rho, pp, with_relres=False)
+            e = rel_max_err(host(outs[i]), po)
+            say(f"{x_stencil} {precision} problem {i} {g.shape}: vs oracle {e:.2e}")
+            assert e <= tol, (i, e)
+            assert infos[i].relres <= (1e-12 if precision == "fp64" else 1e-10)
+
+
+@pytest.mark.parametrize("executor", ["passes", "persistent"])
+def test_batch64_autotuned(gpu, executor, tmp_path, monkeypatch):
+    """The 64-problem batch with every problem's launch shapes tuned
+    (autotune = 2: lines per forward and inverse x block, chunk rows and the
+    stencil variant of its grid): each problem matches the batch in built-in
+    shapes, a sample matches the FP64 oracle, and the shapes the batch ran
+    with are the ones a plan of the same grid reads back from the cache."""
+    monkeypatch.setenv("PSV_AUTOTUNE_CACHE", str(tmp_path / "tune.txt"))
+    cases = W.batch()
+    grids = [gpu.Grid.from_spec(c.grid) for c in cases]
+    ins = []
+    for c in cases:
+        g = O.Grid.from_spec(c.grid)
+        ins.append((g, O.divergence_of_faces(*c.faces, g),
+                    O.mixture_density(c.phi, c.rho_gas, c.rho_liq), c.p_prev))
+    fs, rs, ps = ([dev(x[j]) for x in ins] for j in (1, 2, 3))
+    tuned = gpu.Batch(grids, precision="mixed", executor=executor, autotune=2)
+    plain = gpu.Batch(grids, precision="mixed", executor=executor, autotune=0)
+    outs, infos = tuned.solve(fs, rs, ps, info=True)
+    outs, infos = tuned.solve(fs, rs, ps, info=True)  # replay
+    ref, _ = plain.solve(fs, rs, ps, info=True)
+    # the grids tuned earlier in this process come from its in-process cache
+    # and add no line to the file
+    cache = tmp_path / "tune.txt"
+    lines = cache.read_text().strip().splitlines() if cache.exists() else []
+    say(f"{executor}: tuned shapes {lines}")
+    assert len(lines) <= len({(g.nx, g.ny, g.nz) for g in grids})
+    shapes = {(g.nx, g.ny, g.nz): gpu.Plan(g, precision="mixed", autotune=1).launch_shape()
+              for g in grids}
+    say(f"  (lines per x block, chunk rows) per grid: {shapes}")
+    assert max(i.relres for i in infos) <= 1e-10
+    for i in range(len(cases)):
+        assert rel_max_err(host(outs[i]), host(ref[i])) <= 1e-8, i
+    sizes = np.array([c.grid.n for c in cases])
+    sample = sorted(set([int(np.argmin(sizes)), int(np.argmax(sizes)), 5, 37]))
+    for i in sample:
+        g, f, rho, pp = ins[i]
+        (po,), _ = O.solve(f, g, rho, pp, with_relres=False)
+        e = rel_max_err(host(outs[i]), po)
+        say(f"  problem {i} {g.shape}: vs oracle {e:.2e}")
+        assert e <= 1e-8

@@ -26,7 +26,7 @@ def tanh_case():
 def test_tanh_256x256x512(gpu, tanh_case, precision):
     case, g, f, rho, pp, po, r = tanh_case
     say(f"256x256x512 tanh {precision}")
-    plan = gpu.Plan(gpu.Grid.from_spec(case.grid), precision=precision, autotune=1)
+    plan = gpu.Plan(gpu.Grid.from_spec(case.grid), precision=precision, autotune=2)
     p, info = plan.solve(dev(f), rho=dev(rho), p_prev=dev(pp), info=True)
     ph = host(p)
     err = rel_max_err(ph, po)
@@ -34,7 +34,7 @@ def test_tanh_256x256x512(gpu, tanh_case, precision):
     say(f"  err vs oracle {err:.3e}, relres {info.relres:.3e} (host {rr:.3e}), steps {info.refine_steps}")
     if precision == "fp64":
         assert info.relres <= 1e-12 and rr <= 1e-12
-        assert err <= 1e-10
+        assert err <= 1e-11
         # as benchmarked: captured in a graph and replayed, bit for bit the eager result
         F, R, P = dev(f), dev(rho), dev(pp)
         out = torch.empty_like(F)
@@ -55,7 +55,7 @@ def test_tanh_256x256x512(gpu, tanh_case, precision):
         del graph
     else:
         assert info.relres <= 1e-10 and rr <= 1e-10
-        assert err <= 1e-7
+        assert err <= 1e-8
 
 
 @pytest.mark.parametrize("precision,h_rho,tol_fd,tol_ref",
@@ -74,7 +74,7 @@ def test_grad_256cubed(gpu, precision, h_rho, tol_fd, tol_ref):
     w = case.w
     rho0 = float(rho.min())
     say(f"grad256 {precision}")
-    plan = gpu.Plan(gpu.Grid.from_spec(case.grid), precision=precision, autotune=1)
+    plan = gpu.Plan(gpu.Grid.from_spec(case.grid), precision=precision, autotune=2)
     F, R, P, Wd = dev(f), dev(rho), dev(pp), dev(w)
     gr = plan.adjoint(Wd, f=F, rho=R, p_prev=P, rho0=rho0, grad_rho0=True)
     ref = O.adjoint_step(w, f, rho, rho0, pp, g)
@@ -84,7 +84,7 @@ def test_grad_256cubed(gpu, precision, h_rho, tol_fd, tol_ref):
     say(f"  vs oracle: grad_f {ef:.2e} grad_rho {er:.2e} grad_rho0 {e0:.2e}")
     assert ef <= tol_ref and er <= tol_ref and e0 <= tol_ref
 
-    fwd = plan if precision == "fp64" else gpu.Plan(gpu.Grid.from_spec(case.grid), autotune=1)
+    fwd = plan if precision == "fp64" else gpu.Plan(gpu.Grid.from_spec(case.grid), autotune=2)
 
     def loss(ff, rr):
         return float((Wd * fwd.solve(ff, rho=rr, p_prev=P, rho0=rho0)).sum())

@@ -112,7 +112,7 @@ def test_vd128_chain_as_benchmarked(gpu):
     case = W.vd128()
     g, f, rho, pp = oracle_inputs(case)
     ps, _ = O.solve(f, g, rho, pp, n_steps=10, with_relres=False)
-    plan = gpu.Plan(gpu.Grid.from_spec(case.grid), autotune=1)
+    plan = gpu.Plan(gpu.Grid.from_spec(case.grid), autotune=2)
     say(f"vd128 graph replay, launch shape {plan.launch_shape()}")
     fd, rd, pd = dev(f), dev(rho), dev(pp)
     out = torch.empty_like(fd)

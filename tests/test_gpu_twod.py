@@ -59,3 +59,23 @@ def test_two_dimensional_method3(gpu):
     assert rel_max_err(host(p), ref.p[2]) <= TOL_FP64
     assert max(rel_max_err(host(a), b) for a, b in zip(u, ref.u)) <= TOL_FP64
     assert abs(info.eps - ref.eps[2]) <= 1e-8 * ref.eps[2]
+
+
+@pytest.mark.parametrize("kc", [4, 8, 16])
+@pytest.mark.parametrize("nz,stretched", [(100, True), (13, False), (3, True)])
+def test_two_dimensional_ragged_chunks(gpu, kc, nz, stretched):
+    """The z passes of ny = 1 problems handle a partial last chunk (nz not a
+    multiple of the chunk rows, and nz below them) for every chunk size, FP64
+    and mixed, against the oracle."""
+    spec = _spec(64, nz, nz / 64, stretched)
+    case = W.two_phase_case("twod_ragged", spec, 1, 23 + nz, n_spheres=2)
+    g, f, rho, pp = oracle_inputs(case)
+    ps, _ = O.solve(f, g, rho, pp, n_steps=2, with_relres=False)
+    for precision, tol in (("fp64", TOL_FP64), ("mixed", 1e-8)):
+        plan = gpu.Plan(gpu.Grid.from_spec(spec), precision=precision, chunk_rows=kc)
+        assert plan.launch_shape()[1] == kc
+        p, info = plan.solve(dev(f), rho=dev(rho), p_prev=dev(pp), n_steps=2, info=True)
+        err = rel_max_err(host(p), ps[1])
+        say(f"2-D ragged nz={nz} kc={kc} {precision}: err {err:.2e} relres {info.relres:.2e}")
+        assert err <= tol
+        assert info.relres <= (1e-12 if precision == "fp64" else 1e-10)
