@@ -262,6 +262,29 @@ psv_status psv_solve_converged_adjoint(psv_plan* plan, const double* w, const do
                                        int32_t max_iter, double* grad_f, double* grad_rho,
                                        void* stream, psv_m3_info* info);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): psv_solve
+ * without a plan. The plan's tables (twiddles, eigenvalues, z geometry,
+ * interface factors) and its workspace (spectrum, partial sums, device scalars
+ * and flags) are carved out of one static device array of
+ * PSV_STATIC_SCRATCH_BYTES per GPU, which the library holds until the process
+ * ends; each call refills the tables from kernel arguments and clears the
+ * scalars and flags with kernels. The call allocates nothing, on the host or
+ * the device, and records no memset. Arguments and results as psv_solve
+ * (FP64, built-in launch shapes: the same passes and bits as a plan created
+ * with autotune = 0), without info. opts may be NULL (defaults); it must have
+ * precision PSV_FP64, autotune 0 and check_inputs 0 (PSV_ERR_INVALID_ARG);
+ * chunk_rows and x_stencil are honoured. Tables and workspace must fit the
+ * array (about 8.8 million cells, e.g. 128^3 with room to spare):
+ * PSV_ERR_UNSUPPORTED_SIZE otherwise, before any device work when the
+ * spectrum alone is too large. Every call on one GPU shares that GPU's array:
+ * calls that overlap in time on one GPU (other streams, other threads) race
+ * and give wrong results, so serialise them. */
+#define PSV_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+psv_status psv_solve_static(const psv_grid* grid, const psv_opts* opts, const double* f,
+                            const double* rho, double rho0, const double* p_prev, double* p_out,
+                            int32_t n_steps, void* stream);
+
 /* Mixture density of Sec. 2.2, Eq. eq_22, with the colour Phi = 1 in gas:
  * rho = rho_gas * Phi + rho_liq * (1 - Phi). phi and rho_gas are device fields. */
 psv_status psv_density_from_colour(const psv_plan* plan, const double* phi, const double* rho_gas,

@@ -71,6 +71,8 @@ EXPORTS = {
     "psv_solve_converged_adjoint": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                               C.c_int32, C.c_double, C.c_int32, C.c_void_p,
                                               C.c_void_p, C.c_void_p, C.POINTER(psv_m3_info)]),
+    "psv_solve_static": (C.c_int, [C.POINTER(psv_grid), C.POINTER(psv_opts), C.c_void_p, C.c_void_p,
+                                   C.c_double, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]),
     "psv_density_from_colour": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_void_p,
                                           C.c_void_p]),
     "psv_divergence": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),

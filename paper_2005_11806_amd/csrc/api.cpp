@@ -27,6 +27,8 @@ void batch_set_io(psv_batch& B, int p, const double* f, const double* rho, const
                   double* pout, double rho0, bool want_r);
 void batch_solve(psv_batch& B, hipStream_t s, bool check);
 bool batch_infos(psv_batch& B, hipStream_t s, psv_info* infos);
+void solve_static(const psv_grid& grid, const psv_opts& o, const double* f, const double* rho,
+                  double rho0, const double* p_prev, double* p_out, int n_steps, hipStream_t s);
 }  // namespace psv
 
 struct psv_plan {
@@ -561,6 +563,31 @@ psv_status psv_solve_converged_adjoint(psv_plan* plan, const double* w, const do
                                       grad_f, grad_rho, nullptr, P.partials, s);
         }
         loop_info(P, s, false, info);
+    });
+}
+
+psv_status psv_solve_static(const psv_grid* grid, const psv_opts* opts, const double* f,
+                            const double* rho, double rho0, const double* p_prev, double* p_out,
+                            int32_t n_steps, void* stream) {
+    return guarded([&] {
+        psv::validate_grid(grid);
+        psv::validate_opts(opts);
+        psv_opts o;
+        if (opts)
+            o = *opts;
+        else
+            psv::default_opts(&o);
+        need(f != nullptr, "f is NULL");
+        need(p_out != nullptr, "p_out is NULL");
+        need(n_steps >= 1, "n_steps must be >= 1");
+        need(std::isfinite(rho0), "rho0 must be finite");
+        need_aligned({f, rho, p_prev, p_out});
+        if (o.method == PSV_SPLIT_RHO0)
+            need(rho != nullptr, "rho is required by Method I");
+        else
+            need(n_steps == 1, "the constant-coefficient solve takes n_steps = 1");
+        psv::solve_static(*grid, o, f, rho, rho0, p_prev, p_out, n_steps,
+                          reinterpret_cast<hipStream_t>(stream));
     });
 }
 

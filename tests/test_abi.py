@@ -128,3 +128,25 @@ def test_defaults_and_status_strings():
     assert o.tol == 1e-10 and o.max_refine == 4
     for code, name in _abi.STATUS_NAMES.items():
         assert lib.psv_status_string(code).decode() == name
+
+
+def test_static_solve_rejects_on_the_host():
+    """The plan-free, allocation-free solve checks its arguments and the size
+    of the static array before any device work."""
+    lib = _abi.load()
+    o = _abi.psv_opts()
+    lib.psv_opts_default(C.byref(o))
+    big, _k = psv.Grid(256, 256, 256)._c()  # spectrum alone exceeds the array
+    x = C.c_void_p(4096)  # never dereferenced: rejected first
+    assert lib.psv_solve_static(C.byref(big), C.byref(o), x, x, 0.0, None, x, 1, None) \
+        == _abi.PSV_ERR_UNSUPPORTED_SIZE
+    assert b"static scratch" in lib.psv_last_error_message()
+    small, _k2 = psv.Grid(16, 16, 8)._c()
+    o.precision = _abi.PSV_MIXED
+    assert lib.psv_solve_static(C.byref(small), C.byref(o), x, x, 0.0, None, x, 1, None) \
+        == _abi.PSV_ERR_INVALID_ARG
+    lib.psv_opts_default(C.byref(o))
+    assert lib.psv_solve_static(C.byref(small), C.byref(o), None, x, 0.0, None, x, 1, None) \
+        == _abi.PSV_ERR_INVALID_ARG
+    assert lib.psv_solve_static(C.byref(small), C.byref(o), x, x, 0.0, None, x, 0, None) \
+        == _abi.PSV_ERR_INVALID_ARG
