@@ -101,11 +101,15 @@ typedef struct {
                                 1 rows staged in LDS, 2 loaded directly (cache-served) */
 } psv_opts;
 
+#define PSV_RELRES_HISTORY 8
 typedef struct {
     int32_t refine_steps;    /* refinement sweeps applied (MIXED) */
     double relres;           /* ||r - L p||_2 / ||r||_2 of the last step, r = projected RHS */
     double rhs_mean_removed; /* volume-weighted mean of the last step's RHS removed by projection */
     double rho0_used;        /* the rho0 of the splitting */
+    double relres_sweep[PSV_RELRES_HISTORY]; /* MIXED, last step of psv_solve: relres after the
+                                FP32 solve (entry 0) and after each refinement sweep (entry i);
+                                NaN past the last sweep, and in FP64 or batched solves */
 } psv_info;
 
 typedef struct psv_plan psv_plan;
@@ -151,7 +155,15 @@ psv_status psv_plan_destroy(psv_plan* plan);
  * rho0 > 0 is used as given; rho0 <= 0 selects min(rho), computed on the device.
  * p_prev may alias p_out. If info != NULL the call synchronises `stream` and
  * fills *info for the last step (relres is computed only then, or always in
- * MIXED precision). */
+ * MIXED precision).
+ * MIXED refinement: each sweep is one fused pass (FP64 residual, its norm, and
+ * the FP32 x transform of the residual), a device-side check of relres
+ * against tol, and the FP32 correction. With info == NULL nothing waits on
+ * the host: max_refine sweeps are enqueued and those after convergence return
+ * on the device at once, so the call can be captured in a graph; a miss of
+ * tol then leaves p at the last iterate without an error. With info != NULL
+ * the host reads the check after every sweep, stops enqueueing at
+ * convergence and returns PSV_ERR_NOT_CONVERGED on a miss. */
 psv_status psv_solve(psv_plan* plan, const double* f, const double* rho, double rho0,
                      const double* p_prev, double* p_out, int32_t n_steps, void* stream,
                      psv_info* info);

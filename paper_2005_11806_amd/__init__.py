@@ -70,6 +70,12 @@ class SolveInfo:
     relres: float
     rhs_mean_removed: float
     rho0_used: float
+    relres_sweep: tuple = ()  # mixed: relres after the FP32 solve and after each sweep
+
+
+def _info(x):
+    hist = tuple(v for v in x.relres_sweep if v == v)  # drop the NaN tail
+    return SolveInfo(x.refine_steps, x.relres, x.rhs_mean_removed, x.rho0_used, hist)
 
 
 @dataclasses.dataclass
@@ -199,7 +205,7 @@ class Plan:
                              _ptr(out, sh, "out"), int(n_steps), _stream(stream),
                              C.byref(inf) if info else None)
         if info:
-            si = SolveInfo(inf.refine_steps, inf.relres, inf.rhs_mean_removed, inf.rho0_used)
+            si = _info(inf)
             if st == _abi.PSV_ERR_NOT_CONVERGED:
                 raise PsvError(st, f"not converged: {si}")
             check(st)
@@ -384,8 +390,7 @@ class Batch:
         infos = (_abi.psv_info * n)() if info else None
         st = lib().psv_batch_solve(self._h, f_a, r_a, r0, p_a, o_a, _stream(stream), infos)
         if info:
-            out_infos = [SolveInfo(x.refine_steps, x.relres, x.rhs_mean_removed, x.rho0_used)
-                         for x in infos]
+            out_infos = [_info(x) for x in infos]
             if st == _abi.PSV_ERR_NOT_CONVERGED:
                 raise PsvError(st, f"not converged: {out_infos}")
             check(st)

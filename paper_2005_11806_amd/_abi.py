@@ -32,9 +32,13 @@ class psv_opts(C.Structure):
                 ("batch_executor", C.c_int32), ("chunk_rows", C.c_int32), ("x_stencil", C.c_int32)]
 
 
+PSV_RELRES_HISTORY = 8
+
+
 class psv_info(C.Structure):
     _fields_ = [("refine_steps", C.c_int32), ("relres", C.c_double),
-                ("rhs_mean_removed", C.c_double), ("rho0_used", C.c_double)]
+                ("rhs_mean_removed", C.c_double), ("rho0_used", C.c_double),
+                ("relres_sweep", C.c_double * PSV_RELRES_HISTORY)]
 
 
 class psv_shape(C.Structure):

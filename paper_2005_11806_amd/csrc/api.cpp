@@ -94,16 +94,22 @@ void check_field(const Plan& P, const double* x, bool positive, const char* name
 // One constant-coefficient solve of the system assembled by `a` (CONST or
 // METHOD1), written to `out`. FP64: five passes (x, y with the z chunk
 // elimination, z interface, y with the back substitution, inverse x).
-// MIXED: the same passes in FP32 followed by FP64 residual refinement until relres <= tol. Returns the
-// number of refinement sweeps (MIXED) and leaves relres in scal[S_RELRES]
-// when it was computed.
+// MIXED: the same passes in FP32, then refinement sweeps until relres <= tol:
+// each sweep's fused pass forms the FP64 residual, its norm and the FP32 x
+// transform of the residual at once; a one-block check turns the norm into
+// relres and sets the device flags; the correction passes (z solve, inverse
+// x accumulating into out) are gated by the done flag. With host_checks the
+// host reads the flags after each check and stops enqueueing at convergence;
+// without, max_refine sweeps are enqueued and nothing waits on the host.
+// relres is left in scal[S_RELRES] when it was computed.
 struct CoreResult {
     int steps = 0;
     bool converged = true;
     bool have_relres = false;
 };
 
-CoreResult solve_core(Plan& P, psv::FwdArgs a, double* out, bool want_relres, hipStream_t s) {
+CoreResult solve_core(Plan& P, psv::FwdArgs a, double* out, bool want_relres, bool host_checks,
+                      hipStream_t s) {
     using namespace psv;
     const bool mixed = P.opts.precision == PSV_MIXED;
     const double inv_scale = 2.0 / ((double)P.nx * P.ny);
@@ -124,38 +130,31 @@ CoreResult solve_core(Plan& P, psv::FwdArgs a, double* out, bool want_relres, hi
         }
         return res;
     }
+    const int* done = P.flags + F_DONE;
     FwdArgs ra{};
     ra.mode = FWD_RESID;
     ra.r_in = P.r_ws;
     ra.pprev = out;
     ra.mean = P.scal + S_RHS_MEAN;
     ra.partials = P.partials;
-    bool fused = true;
+    ra.done = done;
+    const int maxr = P.opts.max_refine;
+    launch_refine_reset(P, s);
     res.have_relres = true;
-    for (;;) {
-        if (fused) {
-            launch_fwd_x(P, true, ra, s);
-            launch_norm_finalize(P, fwd_x_blocks(P), 0.0, s);
-        } else {
-            launch_residual(P, P.r_ws, out, P.scal + S_RHS_MEAN, s);
+    for (int sweep = 0;; ++sweep) {
+        launch_fwd_x(P, true, ra, s);
+        launch_refine_check(P, fwd_x_blocks(P), sweep, maxr, P.opts.tol, s);
+        if (host_checks) {
+            sync_read(P, s);
+            if (P.host_flags[F_DONE]) break;
         }
-        sync_read(P, s);
-        const double rr = P.host_scal[S_RELRES];
-        if (rr <= P.opts.tol) {
-            res.converged = true;
-            break;
-        }
-        if (res.steps >= P.opts.max_refine || !std::isfinite(rr)) {
-            res.converged = false;
-            break;
-        }
-        if (!fused) {
-            launch_fwd_x(P, true, ra, s);
-        }
-        launch_z_solve(P, true, P.scal + S_MEAN2, nullptr, s);
-        launch_inv_x(P, true, INV_ADD, out, inv_scale, nullptr, s);
-        res.steps++;
-        fused = false;
+        if (sweep == maxr) break;
+        launch_z_solve(P, true, P.scal + S_MEAN2, done, s);
+        launch_inv_x(P, true, INV_ADD, out, inv_scale, done, s);
+    }
+    if (host_checks) {
+        res.steps = P.host_flags[F_STEPS];
+        res.converged = P.host_flags[F_CONV] != 0;
     }
     return res;
 }
@@ -303,29 +302,28 @@ psv_status psv_solve(psv_plan* plan, const double* f, const double* rho, double 
         a.mode = method1 ? psv::FWD_METHOD1 : psv::FWD_CONST;
         CoreResult cr;
         int total_steps = 0;
-        for (int step = 0; step < n_steps; ++step) {
-            a.pprev = (step == 0) ? p_prev : p_out;
-            const bool last = step + 1 == n_steps;
-            cr = solve_core(P, a, p_out, last && info != nullptr, s);
-            total_steps += cr.steps;
-            if (!cr.converged) {
-                if (info) {
-                    sync_read(P, s);
-                    info->refine_steps = total_steps;
-                    info->relres = P.host_scal[psv::S_RELRES];
-                    info->rhs_mean_removed = P.host_scal[psv::S_RHS_MEAN];
-                    info->rho0_used = P.host_scal[psv::S_RHO0];
-                }
-                psv::fail(PSV_ERR_NOT_CONVERGED, "mixed-precision refinement reached max_refine");
-            }
-        }
-        if (info) {
+        auto fill_info = [&] {
             sync_read(P, s);
             info->refine_steps = total_steps;
             info->relres = cr.have_relres ? P.host_scal[psv::S_RELRES] : NAN;
             info->rhs_mean_removed = P.host_scal[psv::S_RHS_MEAN];
             info->rho0_used = P.host_scal[psv::S_RHO0];
+            const bool mixed = P.opts.precision == PSV_MIXED;
+            for (int i = 0; i < PSV_RELRES_HISTORY; ++i)
+                info->relres_sweep[i] = mixed ? P.host_scal[psv::S_HIST + i] : NAN;
+            if (!mixed && cr.have_relres) info->relres_sweep[0] = info->relres;
+        };
+        for (int step = 0; step < n_steps; ++step) {
+            a.pprev = (step == 0) ? p_prev : p_out;
+            const bool last = step + 1 == n_steps;
+            cr = solve_core(P, a, p_out, last && info != nullptr, info != nullptr, s);
+            total_steps += cr.steps;
+            if (!cr.converged) {
+                if (info) fill_info();
+                psv::fail(PSV_ERR_NOT_CONVERGED, "mixed-precision refinement reached max_refine");
+            }
         }
+        if (info) fill_info();
     });
 }
 
@@ -346,7 +344,7 @@ psv_status psv_solve_adjoint(psv_plan* plan, const double* w, const double* f, c
         a.mode = psv::FWD_CONST;
         a.f = w;
         a.scale = P.t.inv_vol;
-        CoreResult cr = solve_core(P, a, x, false, s);
+        CoreResult cr = solve_core(P, a, x, false, true, s);
         if (!cr.converged) psv::fail(PSV_ERR_NOT_CONVERGED, "mixed-precision refinement reached max_refine");
         if (!method1) {
             if (grad_f) psv::launch_scale_vol(P, x, grad_f, s);

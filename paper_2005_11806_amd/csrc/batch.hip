@@ -794,6 +794,7 @@ bool batch_infos(psv_batch& B, hipStream_t s, psv_info* infos) {
         infos[p].relres = P.host_scal[S_RELRES];
         infos[p].rhs_mean_removed = P.host_scal[S_RHS_MEAN];
         infos[p].rho0_used = P.host_scal[S_RHO0];
+        for (int i = 0; i < PSV_RELRES_HISTORY; ++i) infos[p].relres_sweep[i] = NAN;
         if (B.fp32 && !(infos[p].relres <= P.opts.tol)) ok = false;
     }
     return ok;

@@ -67,7 +67,9 @@ enum Scalar : int {
     S_UNIT = 10,       // the constant 1 (weight of the implicit adjoint's face products)
     S_RHOMAX = 11,     // max rho (Method II weight)
     S_OMEGA = 12,      // Method II weight: harmonic mean of min rho and max rho
-    S_NSCAL = 16
+    S_HIST = 16,       // mixed refinement: relres after the FP32 solve and after each sweep
+    S_NHIST = PSV_RELRES_HISTORY,
+    S_NSCAL = 32
 };
 enum Flag : int { F_DONE = 0, F_ARGMIN = 1, F_STEPS = 2, F_CONV = 3, F_NFLAG = 8 };
 
@@ -221,6 +223,14 @@ void launch_harmonic_weight(const Plan& p, const double* rho, hipStream_t s);
 void launch_min_reduce(const Plan& p, const double* x, double* out_scalar, int* argmin_out,
                        hipStream_t s);
 void launch_norm_finalize(const Plan& p, int nblocks, double tol, hipStream_t s);
+// Mixed refinement on the device: reset clears flags[F_DONE], F_STEPS, F_CONV
+// and the relres history; check (skipped once F_DONE is set) turns the
+// residual pass's partials into relres, records it as history entry `sweep`,
+// and sets F_DONE and F_CONV when relres <= tol, F_DONE alone when sweep ==
+// max_refine or relres is not finite, else counts a sweep in F_STEPS.
+void launch_refine_reset(const Plan& p, hipStream_t s);
+void launch_refine_check(const Plan& p, int nblocks, int sweep, int max_refine, double tol,
+                         hipStream_t s);
 void launch_residual(const Plan& p, const double* r, const double* p_sol, const double* mean,
                      hipStream_t s);
 // Blocks of the forward x pass (also the number of per-block partial sums it writes).

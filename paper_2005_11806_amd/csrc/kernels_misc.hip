@@ -20,9 +20,9 @@ __global__ void __launch_bounds__(RB) k_min_partial(const double* __restrict__ x
     __shared__ int si[RB];
     double best = __builtin_inf();
     int bi = 0x7fffffff;
-    // pairs (16-byte loads), four in flight, visited in increasing index
+    // pairs (16-byte loads), eight in flight, visited in increasing index
     // order so that a strict '<' keeps the first minimum
-    constexpr int U = 4;
+    constexpr int U = 8;
     const double2* x2 = reinterpret_cast<const double2*>(x);
     const size_t n2 = n / 2, stride = (size_t)gridDim.x * RB;
     size_t c = (size_t)blockIdx.x * RB + threadIdx.x;
@@ -65,12 +65,12 @@ __global__ void __launch_bounds__(RB) k_min_partial(const double* __restrict__ x
     }
 }
 
-// Largest value (no index), pairs of doubles, four in flight per thread.
+// Largest value (no index), pairs of doubles, eight in flight per thread.
 __global__ void __launch_bounds__(RB) k_max_partial(const double* __restrict__ x, size_t n,
                                                     double* pv) {
     __shared__ double sv[RB];
     double best = -__builtin_inf();
-    constexpr int U = 4;
+    constexpr int U = 8;
     const double2* x2 = reinterpret_cast<const double2*>(x);
     const size_t n2 = n / 2, stride = (size_t)gridDim.x * RB;
     size_t c = (size_t)blockIdx.x * RB + threadIdx.x;
@@ -160,6 +160,43 @@ __global__ void k_relres_final(double* scal, int* flags, double tol) {
         const double rr = r2 > 0.0 ? sqrt(scal[S_RES2] / r2) : 0.0;
         scal[S_RELRES] = rr;
         if (tol > 0.0 && rr <= tol) flags[F_DONE] = 1;
+    }
+}
+
+__global__ void k_refine_reset(double* scal, int* flags) {
+    if (threadIdx.x < S_NHIST) scal[S_HIST + threadIdx.x] = __builtin_nan("");
+    if (threadIdx.x == 0) {
+        flags[F_DONE] = 0;
+        flags[F_STEPS] = 0;
+        flags[F_CONV] = 0;
+    }
+}
+
+__global__ void __launch_bounds__(RB) k_refine_check(const double* partials, int nb, int sweep,
+                                                     int max_refine, double tol, double* scal,
+                                                     int* flags) {
+    __shared__ double sh[16];
+    if (flags[F_DONE]) return;  // uniform over the block
+    double a = 0.0, b = 0.0;
+    for (int i = threadIdx.x; i < nb; i += RB) {
+        a += partials[2 * (size_t)i];
+        b += partials[2 * (size_t)i + 1];
+    }
+    a = block_sum(a, sh);
+    __syncthreads();
+    b = block_sum(b, sh);
+    if (threadIdx.x == 0) {
+        const double rr = b > 0.0 ? sqrt(a / b) : 0.0;
+        scal[S_RELRES] = rr;
+        if (sweep < S_NHIST) scal[S_HIST + sweep] = rr;
+        if (rr <= tol) {
+            flags[F_DONE] = 1;
+            flags[F_CONV] = 1;
+        } else if (sweep >= max_refine || !isfinite(rr)) {
+            flags[F_DONE] = 1;
+        } else {
+            flags[F_STEPS] += 1;
+        }
     }
 }
 
@@ -601,6 +638,18 @@ void launch_norm_finalize(const Plan& p, int nblocks, double tol, hipStream_t s)
     hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(RB), 0, s, p.partials, nblocks, 2,
                        p.scal + S_RES2);
     hipLaunchKernelGGL(k_relres_final, dim3(1), dim3(64), 0, s, p.scal, p.flags, tol);
+    PSV_HIP(hipGetLastError());
+}
+
+void launch_refine_reset(const Plan& p, hipStream_t s) {
+    hipLaunchKernelGGL(k_refine_reset, dim3(1), dim3(64), 0, s, p.scal, p.flags);
+    PSV_HIP(hipGetLastError());
+}
+
+void launch_refine_check(const Plan& p, int nblocks, int sweep, int max_refine, double tol,
+                         hipStream_t s) {
+    hipLaunchKernelGGL(k_refine_check, dim3(1), dim3(RB), 0, s, p.partials, nblocks, sweep,
+                       max_refine, tol, p.scal, p.flags);
     PSV_HIP(hipGetLastError());
 }
 

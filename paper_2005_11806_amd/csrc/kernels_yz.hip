@@ -87,7 +87,7 @@ __global__ void __launch_bounds__(TAB_THREADS) k_ifc_table(ZArgs z, T* __restric
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int s = blockIdx.x * TAB_THREADS + (int)threadIdx.x;
     if (s >= z.mx * z.ny) return;
-    c2<T>* scratch = reinterpret_cast<c2<T>*>(smem_raw) + threadIdx.x;
+    c2<double>* scratch = reinterpret_cast<c2<double>*>(smem_raw) + threadIdx.x;
     ifc_table_pair<T>(z, s, tab, scratch, TAB_THREADS);
 }
 
@@ -184,7 +184,7 @@ void launch_ifc_table(const Plan& p, hipStream_t s) {
     const bool fp32 = p.opts.precision == PSV_MIXED;
     const ZArgs z = make_zargs(p, nullptr);
     const int nblk = (p.mx * p.ny + TAB_THREADS - 1) / TAB_THREADS;
-    const size_t lds = (size_t)p.lp.kc * TAB_THREADS * (fp32 ? sizeof(float2) : sizeof(double2));
+    const size_t lds = (size_t)p.lp.kc * TAB_THREADS * sizeof(double2);
     if (fp32) {
         allow_lds(k_ifc_table<float>, lds);
         hipLaunchKernelGGL(k_ifc_table<float>, dim3(nblk), dim3(TAB_THREADS), lds, s, z,

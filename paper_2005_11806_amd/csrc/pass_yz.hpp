@@ -531,11 +531,16 @@ __device__ __forceinline__ void ifc_tile(const ZArgs& z, c2<T>* __restrict__ spe
 // scratch per thread in LDS at [i][thread]): the coefficients (A, C) of the
 // first and last row of every chunk, from the same sweeps as the y tiles,
 // then the Thomas factors c'_r = C_r / den_r, 1/den_r with
-// den_r = 1 - A_r c'_{r-1} (den_0 = 1).
+// den_r = 1 - A_r c'_{r-1} (den_0 = 1). Computed in FP64 whatever the
+// spectrum's precision and stored in it: for the near-singular low
+// wavenumber pairs den_r is a difference of nearly equal terms, and an FP32
+// recurrence would spoil the corrections of the mixed refinement (256x256x512
+// tanh grid: relres 1.8e-10 after one sweep, against 1.1e-11 with the FP64
+// table).
 template <typename T>
-__device__ __forceinline__ void ifc_table_pair(const ZArgs& z, int s, T* tab, c2<T>* scratch,
+__device__ __forceinline__ void ifc_table_pair(const ZArgs& z, int s, T* tab, c2<double>* scratch,
                                                int sstride) {
-    using C = c2<T>;
+    using C = c2<double>;
     const int S = z.mx * z.ny;
     const int R = 2 * z.nc;
     T* tA = tab;
@@ -544,40 +549,40 @@ __device__ __forceinline__ void ifc_table_pair(const ZArgs& z, int s, T* tab, c2
     const int m = s / z.ny, n = s - m * z.ny;
     const double lam = z.lamx[m] + z.lamy[n];
     const int kc = z.kc;
-    T cprev = (T)0;
+    double cprev = 0.0;
     for (int c = 0; c < z.nc; ++c) {
         const int k0 = c * kc;
-        T aa = (T)0, cc = (T)0;
+        double aa = 0.0, cc = 0.0;
         for (int i = 0; i < kc; ++i) {
             const ZRow row = zrow(z, k0 + i, lam);
-            T na, ncc;
-            (void)chunk_fwd<T>(i, row, aa, cc, na, ncc);
+            double na, ncc;
+            (void)chunk_fwd<double>(i, row, aa, cc, na, ncc);
             scratch[i * sstride] = C{na, ncc};
             aa = na;
             cc = ncc;
         }
         const C w0 = scratch[0];
         const C wl = scratch[(kc - 1) * sstride];
-        T A0 = w0.x, C0 = w0.y;
+        double A0 = w0.x, C0 = w0.y;
         if (kc >= 3) {
-            T ab = scratch[(kc - 2) * sstride].x, cb = scratch[(kc - 2) * sstride].y;
+            double ab = scratch[(kc - 2) * sstride].x, cb = scratch[(kc - 2) * sstride].y;
             for (int i = kc - 3; i >= 1; --i) {
                 const C wi = scratch[i * sstride];
-                chunk_bwd<T>(wi.x, wi.y, ab, cb);
+                chunk_bwd<double>(wi.x, wi.y, ab, cb);
             }
-            const T r0 = chunk_row0_pivot<T>(w0.y, ab);
+            const double r0 = chunk_row0_pivot<double>(w0.y, ab);
             A0 = w0.x * r0;
             C0 = -w0.y * cb * r0;
         }
-        const T rowA[2] = {A0, wl.x};
-        const T rowC[2] = {C0, wl.y};
+        const double rowA[2] = {A0, wl.x};
+        const double rowC[2] = {C0, wl.y};
         for (int e = 0; e < 2; ++e) {
             const int r = 2 * c + e;
-            const T inv = r == 0 ? (T)1 : (T)1 / ((T)1 - rowA[e] * cprev);
+            const double inv = r == 0 ? 1.0 : 1.0 / (1.0 - rowA[e] * cprev);
             cprev = rowC[e] * inv;
-            tA[(size_t)r * S + s] = rowA[e];
-            tC[(size_t)r * S + s] = cprev;
-            tI[(size_t)r * S + s] = inv;
+            tA[(size_t)r * S + s] = (T)rowA[e];
+            tC[(size_t)r * S + s] = (T)cprev;
+            tI[(size_t)r * S + s] = (T)inv;
         }
     }
 }

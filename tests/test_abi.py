@@ -33,7 +33,7 @@ def test_library_exports_every_declared_function():
 def test_struct_layouts_match_header():
     assert C.sizeof(_abi.psv_grid) == 3 * 4 + 4 + 3 * 8 + 8 + 8  # ints, pad, doubles, ptr, enum+pad
     assert C.sizeof(_abi.psv_opts) == 8 + 8 + 6 * 4  # precision, method, tol, 6 ints
-    assert C.sizeof(_abi.psv_info) == 8 + 3 * 8
+    assert C.sizeof(_abi.psv_info) == 8 + 3 * 8 + _abi.PSV_RELRES_HISTORY * 8
 
 
 def _status(g):
