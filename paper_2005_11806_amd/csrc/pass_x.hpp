@@ -68,13 +68,13 @@ inline size_t x_lds_max(int nx, int lb) {
 // rho_f = (rho_L + rho_R)/2, i.e. (s - 2 rho0)/s with s = rho_L + rho_R.
 __device__ __forceinline__ double bflux(double rl, double rr, double pl, double pr, double two_r0) {
     const double s = rl + rr;
-    return (s - two_r0) * rcp_nr(s) * (pr - pl);
+    return (s - two_r0) * rcp_nr1(s) * (pr - pl);
 }
 
 // rho_f^-1 (p_R - p_L) across the face between cells L and R,
 // rho_f = (rho_L + rho_R)/2.
 __device__ __forceinline__ double gflux(double rl, double rr, double pl, double pr) {
-    return 2.0 * rcp_nr(rl + rr) * (pr - pl);
+    return 2.0 * rcp_nr1(rl + rr) * (pr - pl);
 }
 
 // 7-point L p at one cell (flux form in z; zero wall flux).
