@@ -346,6 +346,28 @@ __device__ __forceinline__ C* lds_fft_n(C* buf0, C* buf1, int L, int nlines, int
     }
 }
 
+// Block copy of n elements (256 threads), G per thread in flight: get(t) is
+// evaluated for G indices before put(t, v) runs for any of them, so their
+// global loads overlap (a plain strided loop waits for each load before the
+// LDS write that follows it). get must accept any t < n; slots past n call
+// it again with the first index of the round and are not put.
+template <int G, typename V, typename Get, typename Put>
+__device__ __forceinline__ void block_copy(int n, Get&& get, Put&& put) {
+    for (int t0 = (int)threadIdx.x; t0 < n; t0 += G * 256) {
+        V v[G];
+#pragma unroll
+        for (int j = 0; j < G; ++j) {
+            const int t = t0 + j * 256;
+            v[j] = get(t < n ? t : t0);
+        }
+#pragma unroll
+        for (int j = 0; j < G; ++j) {
+            const int t = t0 + j * 256;
+            if (t < n) put(t, v[j]);
+        }
+    }
+}
+
 // Block-wide sum of one double per thread (blockDim.x <= 1024, multiple of 64).
 __device__ inline double block_sum(double v, double* sh) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);

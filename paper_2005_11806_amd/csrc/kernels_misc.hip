@@ -12,16 +12,40 @@ namespace psv {
 namespace {
 
 constexpr int RB = 256;      // threads per reduction block
-constexpr int RMAXB = 1024;  // partial blocks of a reduction
+constexpr int RMAXB = 2048;  // partial blocks of a reduction
 
+// (value, index) pair that comes first: smaller value, then smaller index
+__device__ __forceinline__ void argmin_merge(double& v, int& i, double v2, int i2) {
+    if (v2 < v || (v2 == v && i2 < i)) {
+        v = v2;
+        i = i2;
+    }
+}
+
+// Block-wide argmin_merge of one pair per thread; the result is on thread 0.
+__device__ __forceinline__ void block_argmin(double& v, int& i, double* sv, int* si) {
+    for (int o = 32; o > 0; o >>= 1) argmin_merge(v, i, __shfl_down(v, o, 64), __shfl_down(i, o, 64));
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) {
+        sv[w] = v;
+        si[w] = i;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int k = 1; k < RB / 64; ++k) argmin_merge(v, i, sv[k], si[k]);
+}
+
+// Per-block minimum of a strided share of x[0, n) and the first index where
+// it occurs (pairs (16-byte loads), eight in flight, visited in increasing
+// index order so that a strict '<' keeps the first minimum). A second launch
+// merges the blocks' pairs: a device-scope fence per block (to merge in the
+// last block instead) writes back its L2 and costs more than the launch.
 __global__ void __launch_bounds__(RB) k_min_partial(const double* __restrict__ x, size_t n,
                                                     double* pv, int* pi) {
-    __shared__ double sv[RB];
-    __shared__ int si[RB];
+    __shared__ double sv[RB / 64];
+    __shared__ int si[RB / 64];
     double best = __builtin_inf();
     int bi = 0x7fffffff;
-    // pairs (16-byte loads), eight in flight, visited in increasing index
-    // order so that a strict '<' keeps the first minimum
     constexpr int U = 8;
     const double2* x2 = reinterpret_cast<const double2*>(x);
     const size_t n2 = n / 2, stride = (size_t)gridDim.x * RB;
@@ -45,23 +69,24 @@ __global__ void __launch_bounds__(RB) k_min_partial(const double* __restrict__ x
         best = x[n - 1];
         bi = (int)(n - 1);
     }
-    sv[threadIdx.x] = best;
-    si[threadIdx.x] = bi;
-    __syncthreads();
-    for (int o = RB / 2; o > 0; o >>= 1) {
-        if (threadIdx.x < o) {
-            const double v = sv[threadIdx.x + o];
-            const int i = si[threadIdx.x + o];
-            if (v < sv[threadIdx.x] || (v == sv[threadIdx.x] && i < si[threadIdx.x])) {
-                sv[threadIdx.x] = v;
-                si[threadIdx.x] = i;
-            }
-        }
-        __syncthreads();
-    }
+    block_argmin(best, bi, sv, si);
     if (threadIdx.x == 0) {
-        pv[blockIdx.x] = sv[0];
-        pi[blockIdx.x] = si[0];
+        pv[blockIdx.x] = best;
+        pi[blockIdx.x] = bi;
+    }
+}
+
+__global__ void __launch_bounds__(RB) k_min_final(const double* pv, const int* pi, int nb,
+                                                  double* out, int* argmin) {
+    __shared__ double sv[RB / 64];
+    __shared__ int si[RB / 64];
+    double best = __builtin_inf();
+    int bi = 0x7fffffff;
+    for (int b = threadIdx.x; b < nb; b += RB) argmin_merge(best, bi, pv[b], pi[b]);
+    block_argmin(best, bi, sv, si);
+    if (threadIdx.x == 0) {
+        *out = best;
+        if (argmin) *argmin = bi;
     }
 }
 
@@ -108,35 +133,6 @@ __global__ void __launch_bounds__(RB) k_harmonic_final(const double* pv, int nb,
         const double a = scal[S_RHO0], b = sv[0];
         scal[S_RHOMAX] = b;
         scal[S_OMEGA] = 2.0 * a * b / (a + b);
-    }
-}
-
-__global__ void __launch_bounds__(RB) k_min_final(const double* pv, const int* pi, int nb,
-                                                  double* out, int* argmin) {
-    __shared__ double sv[RB];
-    __shared__ int si[RB];
-    double best = __builtin_inf();
-    int bi = 0x7fffffff;
-    for (int b = threadIdx.x; b < nb; b += RB) {
-        if (pv[b] < best || (pv[b] == best && pi[b] < bi)) { best = pv[b]; bi = pi[b]; }
-    }
-    sv[threadIdx.x] = best;
-    si[threadIdx.x] = bi;
-    __syncthreads();
-    for (int o = RB / 2; o > 0; o >>= 1) {
-        if (threadIdx.x < o) {
-            const double v = sv[threadIdx.x + o];
-            const int i = si[threadIdx.x + o];
-            if (v < sv[threadIdx.x] || (v == sv[threadIdx.x] && i < si[threadIdx.x])) {
-                sv[threadIdx.x] = v;
-                si[threadIdx.x] = i;
-            }
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        *out = sv[0];
-        if (argmin) *argmin = si[0];
     }
 }
 

@@ -177,7 +177,7 @@ bool kc_fits(const Plan& p, int kc) {
 size_t ifc_table_bytes(const Plan& p, int kc) {
     const size_t esz = p.opts.precision == PSV_MIXED ? sizeof(float) : sizeof(double);
     const int nc = (p.nz + kc - 1) / kc;
-    return (size_t)3 * 2 * nc * p.mx * p.ny * esz;
+    return ifc_tab_entries(ifc_shape(nc, p.mx * p.ny)) * esz;
 }
 
 void launch_ifc_table(const Plan& p, hipStream_t s) {

@@ -434,16 +434,25 @@ __device__ __forceinline__ void inv_x_tile(const XGeom& g, const c2<TC>* __restr
     C* buf0 = reinterpret_cast<C*>(smem);
     C* xb = buf0 + xbuf_span(g.lb * M);  // lb x (M+1), later reused as the FFT's second buffer
     C* tw = xb + inv_x_stage_span(M, g.lb);
-    for (int t = threadIdx.x; t < 2 * M; t += 256) tw[t] = tw_g[t];
     const size_t plane_s = (size_t)g.mx * g.ny;
     const int nin = (M + 1) * g.lb;
-    for (int t = threadIdx.x; t < nin; t += 256) {
-        const int m = t / g.lb;
-        const int line = t - m * g.lb;
-        C x = cconv<C>(spec[(size_t)k * plane_s + (size_t)m * g.ny + j0 + line]);
-        if (m == 0 || m == M) x.y = (TC)0;  // a real field has real DC and Nyquist bins
-        xb[line * (M + 1) + m] = x;
-    }
+    // one index space: the lb lines' M + 1 bins, then the 2 M twiddles
+    const c2<TS>* sk = spec + (size_t)k * plane_s + j0;
+    block_copy<4, C>(
+        nin + 2 * M,
+        [&](int t) {
+            const int m = t / g.lb;
+            return t < nin ? cconv<C>(sk[(size_t)m * g.ny + (t - m * g.lb)]) : tw_g[t - nin];
+        },
+        [&](int t, C x) {
+            if (t < nin) {
+                const int m = t / g.lb;
+                if (m == 0 || m == M) x.y = (TC)0;  // a real field has real DC and Nyquist bins
+                xb[(t - m * g.lb) * (M + 1) + m] = x;
+            } else {
+                tw[t - nin] = x;
+            }
+        });
     __syncthreads();
     // Z_m = E_m + i O_m with E_m = (X_m + conj X_{M-m}) / 2 and
     // O_m = (X_m - conj X_{M-m}) exp(+2 pi i m / nx) / 2, m = 0..M-1.

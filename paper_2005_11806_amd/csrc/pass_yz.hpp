@@ -73,7 +73,7 @@ struct ZArgs {
     const double* h;
     const double* g;  // centre gaps, g[k] between cells k-1 and k
     double* rhs_mean;
-    const void* tab;  // interface factors, 3 arrays [2 nc][mx ny] in the spectrum's precision
+    const void* tab;  // interface factors (layout: ifc_tab_index), in the spectrum's precision
 };
 
 // Row k of the system with eigenvalue sum lam; rows k >= nz pad the last
@@ -218,11 +218,22 @@ __device__ __forceinline__ void yz_load(const ZArgs& z, const c2<T>* __restrict_
     using C = c2<T>;
     using P = YzLayout<N>;
     const int ny = N ? N : z.ny;
-    for (int t = threadIdx.x; t < ny; t += 256) tw[t] = tw_g[t];
-    for (int e = threadIdx.x; e < KC * ny; e += 256) {
-        const int i = e / ny, n = e - i * ny;
-        buf[P::at(e)] = i < nl ? base[(size_t)i * SP + n] : C{(T)0, (T)0};
-    }
+    // one index space: the KC lines, then the ny twiddles; rows past nl
+    // load row 0 and are stored as 0
+    const int nel = KC * ny;
+    constexpr int G = N > 0 ? ((KC + 1) * N + 255) / 256 < 16 ? ((KC + 1) * N + 255) / 256 : 16 : 8;
+    block_copy<G, C>(
+        nel + ny,
+        [&](int e) {
+            const int i = e / ny, n = e - i * ny;
+            return e < nel ? base[(size_t)(i < nl ? i : 0) * SP + n] : tw_g[e - nel];
+        },
+        [&](int e, C v) {
+            if (e < nel)
+                buf[P::at(e)] = e / ny < nl ? v : C{(T)0, (T)0};
+            else
+                tw[e - nel] = v;
+        });
     __syncthreads();
 }
 
@@ -394,6 +405,36 @@ __host__ __device__ inline int ifc_lanes(int R) {
     return L;
 }
 
+// Interface systems of one wavenumber pair: R = 2 nc rows on L lanes of a
+// wave, Q consecutive rows per lane, spw = 64 / L systems per wave; W waves
+// cover the S = mx ny pairs.
+struct IfcShape {
+    int R, L, Q, spw, W;
+};
+__host__ __device__ inline IfcShape ifc_shape(int nc, int S) {
+    IfcShape h;
+    h.R = 2 * nc;
+    h.L = ifc_lanes(h.R);
+    h.Q = (h.R + h.L - 1) / h.L;
+    h.spw = 64 / h.L;
+    h.W = (S + h.spw - 1) / h.spw;
+    return h;
+}
+
+// Factor table layout, wave-blocked: for the wave of systems [w spw, (w+1)
+// spw), row slot j < Q and component c (0: -A_r / den_r, 1: -c'_r (0 on the
+// last row), 2: 1 / den_r), 64 consecutive entries, one per lane
+// (lane = g spw + s - w spw for row r = g Q + j). Each table load of a wave
+// is then one contiguous 64-entry access. Slots of no row (s >= S or
+// r >= R) are loaded and discarded.
+__host__ __device__ inline size_t ifc_tab_index(const IfcShape& h, int s, int r, int c) {
+    const int w = s / h.spw, g = r / h.Q, j = r - g * h.Q;
+    return (((size_t)w * h.Q + j) * 3 + c) * 64 + g * h.spw + (s - w * h.spw);
+}
+__host__ __device__ inline size_t ifc_tab_entries(const IfcShape& h) {
+    return (size_t)h.W * h.Q * 3 * 64;
+}
+
 // One interface system on L lanes of a wave, Q <= QM consecutive rows per
 // lane (rows g Q .. g Q + Q - 1 on the lane of group g). With the plan-time
 // Thomas factors both sweeps are first-order affine recurrences,
@@ -409,38 +450,40 @@ template <typename T, int QM>
 __device__ __forceinline__ void ifc_scan(const ZArgs& z, c2<T>* __restrict__ spec, int b) {
     using C = c2<T>;
     const int S = z.mx * z.ny;
-    const int R = 2 * z.nc;
-    const int L = ifc_lanes(R);
-    const int spw = 64 / L;  // systems per wave
+    const IfcShape h = ifc_shape(z.nc, S);
+    const int R = h.R, L = h.L, Q = h.Q, spw = h.spw;
     const int lane = (int)threadIdx.x & 63;
     const int g = lane / spw;
-    const int s = (b - 1) * (IFC_THREADS / L) + ((int)threadIdx.x >> 6) * spw + (lane - g * spw);
+    // the wave's first system, and its block of the factor table (the last
+    // tile's waves past S read the last block and discard it)
+    const int sw = __builtin_amdgcn_readfirstlane((b - 1) * (IFC_THREADS / L) +
+                                                  ((int)threadIdx.x >> 6) * spw);
+    const int s = sw + (lane - g * spw);
     const bool act = s < S && s != 0;
-    const int Q = (R + L - 1) / L;
     const int r0 = g * Q;
+    const T* tw = reinterpret_cast<const T*>(z.tab) +
+                  (size_t)min(sw / spw, h.W - 1) * Q * 3 * 64 + lane;
     // 32-bit element offsets (every index here is below nx ny nz < 2^31)
-    const T* tA = reinterpret_cast<const T*>(z.tab);
-    const T* tC = tA + (size_t)R * S;
-    const T* tI = tC + (size_t)R * S;
     const unsigned us = (unsigned)s, uS = (unsigned)S;
     T al[QM], cm[QM];  // forward -A_r I_r, backward -c'_r (identity 1 on padding)
     C d[QM];           // I_r D_r, then d'_r (0 on padding)
+    // Every slot is loaded unconditionally (slots j >= Q read slot 0; the
+    // right-hand side of a slot without a row reads spectrum element s0 of
+    // plane 0) and masked afterwards, so that all 4 QM loads of a lane are
+    // in flight together; loads under per-row branches would each wait.
+    const unsigned s0 = act ? us : 1u;
 #pragma unroll
     for (int j = 0; j < QM; ++j) {
         const int r = r0 + j;
-        al[j] = (T)1;
-        cm[j] = (T)1;
-        d[j] = C{(T)0, (T)0};
-        if (act && j < Q && r < R) {
-            const unsigned o = (unsigned)r * uS + us;
-            const T I = tI[o];
-            al[j] = -tA[o] * I;
-            cm[j] = r < R - 1 ? -tC[o] : (T)0;
-            if (ifc_plane(z, r) < z.nz) {
-                const C D = spec[(unsigned)ifc_plane(z, r) * uS + us];
-                d[j] = C{I * D.x, I * D.y};
-            }
-        }
+        const bool row = act && j < Q && r < R;
+        const bool rhs = row && ifc_plane(z, r) < z.nz;
+        const T* tj = tw + (size_t)(j < Q ? j : 0) * 3 * 64;
+        const unsigned od = rhs ? (unsigned)ifc_plane(z, r) * uS + us : s0;
+        const T A = tj[0], Cc = tj[64], I = tj[128];
+        const C D = spec[od];
+        al[j] = row ? A : (T)1;
+        cm[j] = row ? Cc : (T)1;
+        d[j] = rhs ? C{I * D.x, I * D.y} : C{(T)0, (T)0};
     }
     // forward: this lane's map d'_{r0-1} -> d'_{r0+Q-1}, then an inclusive scan
     T fa = (T)1;
@@ -531,7 +574,8 @@ __device__ __forceinline__ void ifc_tile(const ZArgs& z, c2<T>* __restrict__ spe
 // scratch per thread in LDS at [i][thread]): the coefficients (A, C) of the
 // first and last row of every chunk, from the same sweeps as the y tiles,
 // then the Thomas factors c'_r = C_r / den_r, 1/den_r with
-// den_r = 1 - A_r c'_{r-1} (den_0 = 1). Computed in FP64 whatever the
+// den_r = 1 - A_r c'_{r-1} (den_0 = 1), stored as the maps of the interface
+// scans: -A_r / den_r, -c'_r, 1 / den_r. Computed in FP64 whatever the
 // spectrum's precision and stored in it: for the near-singular low
 // wavenumber pairs den_r is a difference of nearly equal terms, and an FP32
 // recurrence would spoil the corrections of the mixed refinement (256x256x512
@@ -542,10 +586,7 @@ __device__ __forceinline__ void ifc_table_pair(const ZArgs& z, int s, T* tab, c2
                                                int sstride) {
     using C = c2<double>;
     const int S = z.mx * z.ny;
-    const int R = 2 * z.nc;
-    T* tA = tab;
-    T* tC = tab + (size_t)R * S;
-    T* tI = tC + (size_t)R * S;
+    const IfcShape h = ifc_shape(z.nc, S);
     const int m = s / z.ny, n = s - m * z.ny;
     const double lam = z.lamx[m] + z.lamy[n];
     const int kc = z.kc;
@@ -580,9 +621,9 @@ __device__ __forceinline__ void ifc_table_pair(const ZArgs& z, int s, T* tab, c2
             const int r = 2 * c + e;
             const double inv = r == 0 ? 1.0 : 1.0 / (1.0 - rowA[e] * cprev);
             cprev = rowC[e] * inv;
-            tA[(size_t)r * S + s] = (T)rowA[e];
-            tC[(size_t)r * S + s] = (T)cprev;
-            tI[(size_t)r * S + s] = (T)inv;
+            tab[ifc_tab_index(h, s, r, 0)] = (T)(-rowA[e] * inv);
+            tab[ifc_tab_index(h, s, r, 1)] = (T)(r < h.R - 1 ? -cprev : 0.0);
+            tab[ifc_tab_index(h, s, r, 2)] = (T)inv;
         }
     }
 }
