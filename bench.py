@@ -304,6 +304,7 @@ def traced_roofline(plan, step, spec):
     traced step fills the trace's event pool and is discarded: creating its
     events leaves gaps between the launches in which the GPU slows down."""
     import torch
+    settle(step)
     plan.trace(True)
     step()
     torch.cuda.synchronize()
@@ -357,6 +358,7 @@ def bench_method3(args):
         return plan.solve_method3(U, T, R, case.dt, eps_t=eps_t, max_iter=500, out=p, u_out=True)
 
     _, _, info = step()
+    settle(step)
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -468,6 +470,7 @@ def bench_converged(args):
         return fi, ai
 
     fi, ai = step()
+    settle(step)
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -520,6 +523,7 @@ def bench_methods2d(args):
         def step(it=it):
             return plan.solve_converged(f, rho, iteration=it, eps_t=eps_t, max_iter=5000, out=p)[1]
         info = step()
+        settle(step)
         for _ in range(args.warmup):
             step()
         torch.cuda.synchronize()
@@ -586,6 +590,7 @@ def bench_batch(args):
 
         def run():
             batch.solve(fs, rs, ps, outs)
+    settle(run)
     for _ in range(args.warmup):
         run()
     torch.cuda.synchronize()
@@ -613,10 +618,29 @@ def bench_batch(args):
     print(json.dumps(line), flush=True)
 
 
-def _timed(run, steps, warmup):
-    """Seconds per call of run(): warmup untimed calls, then exactly `steps`
-    calls between two device synchronisations."""
+SETTLE_S = 0.3
+
+
+def settle(run):
+    """Untimed calls of run() for about SETTLE_S seconds: after the host-side
+    set-up the GPU starts at lower clocks, and the first few dozen solves of a
+    256x256x512 grid run up to 40% slower than the steady state that a
+    sustained job sees (per-dispatch kernel traces show the ramp)."""
     import torch
+    t0 = time.perf_counter()
+    while True:
+        for _ in range(10):
+            run()
+        torch.cuda.synchronize()
+        if time.perf_counter() - t0 >= SETTLE_S:
+            return
+
+
+def _timed(run, steps, warmup):
+    """Seconds per call of run(): the settle phase, warmup untimed calls, then
+    exactly `steps` calls between two device synchronisations."""
+    import torch
+    settle(run)
     for _ in range(warmup):
         run()
     torch.cuda.synchronize()
@@ -758,8 +782,9 @@ def bench_headline(args):
     ms = 1e3 * t
     p64 = out.cpu().numpy()
 
-    # per-kernel event timing over an eager pass of the same K steps, after one
-    # discarded pass that fills the trace's event pool
+    # per-kernel event timing over an eager pass of the same K steps, after the
+    # settle phase and one discarded pass that fills the trace's event pool
+    settle(step)
     plan.trace(True)
     for rep in range(2):
         for _ in range(args.steps):
@@ -939,6 +964,7 @@ def main():
     else:
         run = step
 
+    settle(run)
     for _ in range(args.warmup):
         run()
     torch.cuda.synchronize()
@@ -950,8 +976,9 @@ def main():
     ms = 1e3 * elapsed / args.steps
     value = spec.n * n_steps * args.steps / elapsed
 
-    # per-kernel event timing over an eager pass of the same K steps, after one
-    # discarded pass that fills the trace's event pool
+    # per-kernel event timing over an eager pass of the same K steps, after the
+    # settle phase and one discarded pass that fills the trace's event pool
+    settle(step)
     plan.trace(True)
     for rep in range(2):
         for _ in range(args.steps):

@@ -350,10 +350,12 @@ __device__ __forceinline__ C* lds_fft_n(C* buf0, C* buf1, int L, int nlines, int
 // evaluated for G indices before put(t, v) runs for any of them, so their
 // global loads overlap (a plain strided loop waits for each load before the
 // LDS write that follows it). get must accept any t < n; slots past n call
-// it again with the first index of the round and are not put.
+// it again with the first index of the round and are not put. The first
+// round is straight-line code: at a loop header the compiler's wait
+// insertion would also wait for loads the caller issued before the copy.
 template <int G, typename V, typename Get, typename Put>
 __device__ __forceinline__ void block_copy(int n, Get&& get, Put&& put) {
-    for (int t0 = (int)threadIdx.x; t0 < n; t0 += G * 256) {
+    auto round = [&](int t0) {
         V v[G];
 #pragma unroll
         for (int j = 0; j < G; ++j) {
@@ -365,7 +367,9 @@ __device__ __forceinline__ void block_copy(int n, Get&& get, Put&& put) {
             const int t = t0 + j * 256;
             if (t < n) put(t, v[j]);
         }
-    }
+    };
+    if ((int)threadIdx.x < n) round((int)threadIdx.x);
+    for (int t0 = (int)threadIdx.x + G * 256; t0 < n; t0 += G * 256) round(t0);
 }
 
 // Block-wide sum of one double per thread (blockDim.x <= 1024, multiple of 64).

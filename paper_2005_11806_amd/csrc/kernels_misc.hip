@@ -35,11 +35,12 @@ __device__ __forceinline__ void block_argmin(double& v, int& i, double* sv, int*
         for (int k = 1; k < RB / 64; ++k) argmin_merge(v, i, sv[k], si[k]);
 }
 
-// Per-block minimum of a strided share of x[0, n) and the first index where
-// it occurs (pairs (16-byte loads), eight in flight, visited in increasing
-// index order so that a strict '<' keeps the first minimum). A second launch
-// merges the blocks' pairs: a device-scope fence per block (to merge in the
-// last block instead) writes back its L2 and costs more than the launch.
+// Per-block minimum of a contiguous share of x[0, n) and the first index
+// where it occurs: pairs (16-byte loads), eight per thread in flight, each
+// thread visiting its pairs in increasing index order so that a strict '<'
+// keeps its first minimum. A second launch merges the blocks' pairs (a
+// device-scope fence per block, to merge in the last block instead, writes
+// back its L2 and costs more than the launch).
 __global__ void __launch_bounds__(RB) k_min_partial(const double* __restrict__ x, size_t n,
                                                     double* pv, int* pi) {
     __shared__ double sv[RB / 64];
@@ -48,19 +49,22 @@ __global__ void __launch_bounds__(RB) k_min_partial(const double* __restrict__ x
     int bi = 0x7fffffff;
     constexpr int U = 8;
     const double2* x2 = reinterpret_cast<const double2*>(x);
-    const size_t n2 = n / 2, stride = (size_t)gridDim.x * RB;
-    size_t c = (size_t)blockIdx.x * RB + threadIdx.x;
-    for (; c + (U - 1) * stride < n2; c += U * stride) {
+    const size_t n2 = n / 2;
+    const size_t chunk = (n2 + gridDim.x - 1) / gridDim.x;
+    const size_t c0 = (size_t)blockIdx.x * chunk;
+    const size_t c1 = c0 + chunk < n2 ? c0 + chunk : n2;
+    size_t c = c0 + threadIdx.x;
+    for (; c + (U - 1) * RB < c1; c += U * RB) {
         double2 v[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) v[u] = x2[c + u * stride];
+        for (int u = 0; u < U; ++u) v[u] = x2[c + u * RB];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            if (v[u].x < best) { best = v[u].x; bi = (int)(2 * (c + u * stride)); }
-            if (v[u].y < best) { best = v[u].y; bi = (int)(2 * (c + u * stride) + 1); }
+            if (v[u].x < best) { best = v[u].x; bi = (int)(2 * (c + u * RB)); }
+            if (v[u].y < best) { best = v[u].y; bi = (int)(2 * (c + u * RB) + 1); }
         }
     }
-    for (; c < n2; c += stride) {
+    for (; c < c1; c += RB) {
         const double2 v = x2[c];
         if (v.x < best) { best = v.x; bi = (int)(2 * c); }
         if (v.y < best) { best = v.y; bi = (int)(2 * c + 1); }

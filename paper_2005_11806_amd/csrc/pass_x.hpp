@@ -119,7 +119,6 @@ __device__ __forceinline__ void fwd_x_tile(const XGeom& g, const Stencil& st, co
     C* buf1 = reinterpret_cast<C*>(smem + off);
     double2* pt = reinterpret_cast<double2*>(smem + off);  // staged p rows (periodic in y)
     double2* rt = pt + (lb + 2) * M;                        // staged rho rows
-    for (int t = threadIdx.x; t < 2 * M; t += 256) tw[t] = tw_g[t];
     const size_t plane = (size_t)nx * g.ny;
 
     const double rho0 = (MODE == FWD_METHOD1) ? *a.rho0 : 0.0;
@@ -224,15 +223,59 @@ __device__ __forceinline__ void fwd_x_tile(const XGeom& g, const Stencil& st, co
     };
     Pre cur[PF];
     prefetch(threadIdx.x, cur);
-    if (MODE != FWD_CONST && STAGE) {
-        for (int t = threadIdx.x; t < (lb + 2) * M; t += 256) {
+    // The twiddles and (with STAGE) the rows j0-1 .. j0+lb of p and rho
+    // (periodic in y; p reads as 0 without an iterate): every load of a thread
+    // is issued before its LDS writes. A p element and the rho element at the
+    // same place share their address; the twiddles of compile-time lengths
+    // wait in registers.
+    {
+        constexpr bool ROWS = MODE != FWD_CONST && STAGE;
+        constexpr bool RHO = MODE == FWD_METHOD1 || MODE == FWD_METHOD3;
+        constexpr int TWP = N > 0 ? (2 * N + 255) / 256 : 1;
+        C twr[TWP];
+        if constexpr (N > 0) {
+#pragma unroll
+            for (int j = 0; j < TWP; ++j) {
+                const int t = (int)threadIdx.x + 256 * j;
+                twr[j] = tw_g[t < 2 * N ? t : 0];
+            }
+        }
+        const int nst = ROWS ? (lb + 2) * M : 0;
+        const size_t kbase = (size_t)k * g.ny * M;
+        auto src = [&](int t) {
             const int rr = t / M;
-            const int q = t - rr * M;
             int j = j0 - 1 + rr;
-            j = (j < 0) ? j + g.ny : (j >= g.ny ? j - g.ny : j);
-            const size_t src = ((size_t)k * g.ny + j) * M + q;
-            pt[t] = has_p ? pg[src] : double2{0.0, 0.0};
-            if (MODE == FWD_METHOD1 || MODE == FWD_METHOD3) rt[t] = rg[src];
+            j += (j < 0) ? g.ny : 0;
+            j -= (j >= g.ny) ? g.ny : 0;
+            return kbase + (size_t)j * M + (t - rr * M);
+        };
+        if constexpr (ROWS && RHO) {
+            struct PR {
+                double2 p, r;
+            };
+            const double2* pv = has_p ? pg : rg;  // a valid array where p is absent
+            block_copy<4, PR>(
+                nst,
+                [&](int t) {
+                    const size_t i = src(t);
+                    return PR{pv[i], rg[i]};
+                },
+                [&](int t, PR v) {
+                    pt[t] = has_p ? v.p : double2{0.0, 0.0};
+                    rt[t] = v.r;
+                });
+        } else if constexpr (ROWS) {
+            block_copy<4, double2>(nst, [&](int t) { return pg[src(t)]; },
+                                   [&](int t, double2 v) { pt[t] = v; });
+        }
+        if constexpr (N > 0) {
+#pragma unroll
+            for (int j = 0; j < TWP; ++j) {
+                const int t = (int)threadIdx.x + 256 * j;
+                if (t < 2 * N) tw[t] = twr[j];
+            }
+        } else {
+            block_copy<2, C>(2 * M, [&](int t) { return tw_g[t]; }, [&](int t, C v) { tw[t] = v; });
         }
         __syncthreads();
     }
