@@ -79,19 +79,35 @@ def residual(ux, uy, uz, div_target, grid):
     return float(np.abs(div(ux, uy, uz, grid) - div_target).sum())
 
 
+def velocity(u_star, p, rho, dt, grid):
+    """u(p) = u* - dt rho_face^-1 G p: the velocity a pressure p gives through
+    the correction step (Eq. corr); u(0) = u*."""
+    return correct(*u_star, p, rho, dt, grid)
+
+
+def step_map(p, u_star, rhs0, rho, dt, grid):
+    """T(p): the pressure that Eq. new_poisson gives when its advective term
+    u . grad rho is taken at u(p), i.e. the constant-coefficient solve of
+    rhs0 - u(p) . grad rho / dt."""
+    u = velocity(u_star, p, rho, dt, grid)
+    return solve_const(rhs0 - advection(*u, rho, grid) / dt, grid)[0]
+
+
 def solve(u_star, div_target, rho, dt, grid, eps_t=1e-14, max_iter=50):
-    """Algorithm 1. u_star = (ux, uy, uz) on faces (uz with nz+1 planes, zero
-    on the walls); returns the iterates, the final velocity and the residuals."""
-    ux, uy, uz = u_star
-    rhs0 = fixed_rhs(ux, uy, uz, div_target, rho, dt, grid)
-    us = (ux, uy, uz)
+    """Method III as the fixed-point iteration p^{s+1} = T(p^s) of step_map,
+    from p^0 = 0 (so u^0 = u*, as Algorithm 1 starts), stopped once the
+    residual of u(p^{s+1}) is at most eps_t or after max_iter maps. u_star =
+    (ux, uy, uz) on faces (uz with nz+1 planes, zero on the walls); returns
+    the iterates, the velocity of the last one and the residuals."""
+    rhs0 = fixed_rhs(*u_star, div_target, rho, dt, grid)
+    p = np.zeros(grid.shape)
     ps, eps = [], []
+    u = tuple(u_star)
     for _ in range(max_iter):
-        r = rhs0 - advection(*us, rho, grid) / dt
-        p, _ = solve_const(r, grid)
-        us = correct(ux, uy, uz, p, rho, dt, grid)
+        p = step_map(p, u_star, rhs0, rho, dt, grid)
+        u = velocity(u_star, p, rho, dt, grid)
         ps.append(p)
-        eps.append(residual(*us, div_target, grid))
+        eps.append(residual(*u, div_target, grid))
         if eps[-1] <= eps_t:
-            return Method3Result(ps, us, eps, True)
-    return Method3Result(ps, us, eps, False)
+            return Method3Result(ps, u, eps, True)
+    return Method3Result(ps, u, eps, False)
