@@ -372,6 +372,17 @@ __device__ __forceinline__ void block_copy(int n, Get&& get, Put&& put) {
     for (int t0 = (int)threadIdx.x + G * 256; t0 < n; t0 += G * 256) round(t0);
 }
 
+// Direct global-to-LDS load of one 16-byte element per active lane (gfx950
+// global_load_lds_dwordx4): lane i of the wave writes lds_base + 16 i bytes,
+// lds_base being the same on every lane. Nothing passes through registers;
+// the data is in LDS after lds_dma_wait() and a block barrier.
+__device__ __forceinline__ void lds_dma16(const void* src, void* lds_base) {
+    __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)lds_base, 16, 0, 0);
+}
+// Waits for this wave's vector memory loads, the direct-to-LDS ones included
+// (vmcnt(0); expcnt and lgkmcnt left at their maxima).
+__device__ __forceinline__ void lds_dma_wait() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
 // Block-wide sum of one double per thread (blockDim.x <= 1024, multiple of 64).
 __device__ inline double block_sum(double v, double* sh) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);

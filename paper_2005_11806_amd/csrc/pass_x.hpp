@@ -224,58 +224,90 @@ __device__ __forceinline__ void fwd_x_tile(const XGeom& g, const Stencil& st, co
     Pre cur[PF];
     prefetch(threadIdx.x, cur);
     // The twiddles and (with STAGE) the rows j0-1 .. j0+lb of p and rho
-    // (periodic in y; p reads as 0 without an iterate): every load of a thread
-    // is issued before its LDS writes. A p element and the rho element at the
-    // same place share their address; the twiddles of compile-time lengths
-    // wait in registers.
+    // (periodic in y; p reads as 0 without an iterate) go to LDS. FP64
+    // compile-time lengths: by direct-to-LDS loads, in 64-entry chunks (one
+    // per wave instruction), the waves taking every fourth chunk; nothing
+    // passes through registers. Otherwise through registers, every load of a
+    // thread issued before its LDS writes: a p element and the rho element at
+    // the same place share their address, and the twiddles of compile-time
+    // lengths wait in registers.
     {
         constexpr bool ROWS = MODE != FWD_CONST && STAGE;
         constexpr bool RHO = MODE == FWD_METHOD1 || MODE == FWD_METHOD3;
-        constexpr int TWP = N > 0 ? (2 * N + 255) / 256 : 1;
-        C twr[TWP];
-        if constexpr (N > 0) {
-#pragma unroll
-            for (int j = 0; j < TWP; ++j) {
-                const int t = (int)threadIdx.x + 256 * j;
-                twr[j] = tw_g[t < 2 * N ? t : 0];
-            }
-        }
+        constexpr bool DMA = std::is_same<TC, double>::value && N > 0;
         const int nst = ROWS ? (lb + 2) * M : 0;
         const size_t kbase = (size_t)k * g.ny * M;
-        auto src = [&](int t) {
-            const int rr = t / M;
+        auto row_j = [&](int rr) {
             int j = j0 - 1 + rr;
             j += (j < 0) ? g.ny : 0;
             j -= (j >= g.ny) ? g.ny : 0;
-            return kbase + (size_t)j * M + (t - rr * M);
+            return j;
         };
-        if constexpr (ROWS && RHO) {
-            struct PR {
-                double2 p, r;
-            };
-            const double2* pv = has_p ? pg : rg;  // a valid array where p is absent
-            block_copy<4, PR>(
-                nst,
-                [&](int t) {
-                    const size_t i = src(t);
-                    return PR{pv[i], rg[i]};
-                },
-                [&](int t, PR v) {
-                    pt[t] = has_p ? v.p : double2{0.0, 0.0};
-                    rt[t] = v.r;
-                });
-        } else if constexpr (ROWS) {
-            block_copy<4, double2>(nst, [&](int t) { return pg[src(t)]; },
-                                   [&](int t, double2 v) { pt[t] = v; });
-        }
-        if constexpr (N > 0) {
-#pragma unroll
-            for (int j = 0; j < TWP; ++j) {
-                const int t = (int)threadIdx.x + 256 * j;
-                if (t < 2 * N) tw[t] = twr[j];
+        if constexpr (DMA) {
+            constexpr int CPR = (N + 63) / 64;        // chunks per row
+            constexpr int CTW = (2 * N + 63) / 64;    // chunks of twiddles
+            const int prow = ROWS && has_p ? lb + 2 : 0;
+            const int nrow = prow + (ROWS && RHO ? lb + 2 : 0);
+            const int nch = nrow * CPR + CTW;
+            const int lane = (int)threadIdx.x & 63;
+            for (int c = (int)threadIdx.x >> 6; c < nch; c += 4) {
+                if (c < nrow * CPR) {
+                    const int row = c / CPR, part = c - row * CPR;
+                    const bool rho_row = row >= prow;
+                    const int rr = rho_row ? row - prow : row;
+                    const size_t sb = kbase + (size_t)row_j(rr) * M + part * 64;
+                    double2* dst = (rho_row ? rt : pt) + rr * M + part * 64;
+                    if (part * 64 + lane < M) lds_dma16((rho_row ? rg : pg) + sb + lane, dst);
+                } else {
+                    const int e = (c - nrow * CPR) * 64;
+                    if (e + lane < 2 * M) lds_dma16(tw_g + e + lane, tw + e);
+                }
             }
+            if (ROWS && !has_p)
+                for (int t = threadIdx.x; t < nst; t += 256) pt[t] = double2{0.0, 0.0};
+            lds_dma_wait();
         } else {
-            block_copy<2, C>(2 * M, [&](int t) { return tw_g[t]; }, [&](int t, C v) { tw[t] = v; });
+            constexpr int TWP = N > 0 ? (2 * N + 255) / 256 : 1;
+            C twr[TWP];
+            if constexpr (N > 0) {
+#pragma unroll
+                for (int j = 0; j < TWP; ++j) {
+                    const int t = (int)threadIdx.x + 256 * j;
+                    twr[j] = tw_g[t < 2 * N ? t : 0];
+                }
+            }
+            auto src = [&](int t) {
+                const int rr = t / M;
+                return kbase + (size_t)row_j(rr) * M + (t - rr * M);
+            };
+            if constexpr (ROWS && RHO) {
+                struct PR {
+                    double2 p, r;
+                };
+                const double2* pv = has_p ? pg : rg;  // a valid array where p is absent
+                block_copy<4, PR>(
+                    nst,
+                    [&](int t) {
+                        const size_t i = src(t);
+                        return PR{pv[i], rg[i]};
+                    },
+                    [&](int t, PR v) {
+                        pt[t] = has_p ? v.p : double2{0.0, 0.0};
+                        rt[t] = v.r;
+                    });
+            } else if constexpr (ROWS) {
+                block_copy<4, double2>(nst, [&](int t) { return pg[src(t)]; },
+                                       [&](int t, double2 v) { pt[t] = v; });
+            }
+            if constexpr (N > 0) {
+#pragma unroll
+                for (int j = 0; j < TWP; ++j) {
+                    const int t = (int)threadIdx.x + 256 * j;
+                    if (t < 2 * N) tw[t] = twr[j];
+                }
+            } else {
+                block_copy<2, C>(2 * M, [&](int t) { return tw_g[t]; }, [&](int t, C v) { tw[t] = v; });
+            }
         }
         __syncthreads();
     }
