@@ -250,7 +250,9 @@ __device__ __forceinline__ void fwd_x_tile(const XGeom& g, const Stencil& st, co
             const int nrow = prow + (ROWS && RHO ? lb + 2 : 0);
             const int nch = nrow * CPR + CTW;
             const int lane = (int)threadIdx.x & 63;
-            for (int c = (int)threadIdx.x >> 6; c < nch; c += 4) {
+            // the chunk arithmetic is the same on every lane of a wave: scalar
+            const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+            for (int c = wave; c < nch; c += 4) {
                 if (c < nrow * CPR) {
                     const int row = c / CPR, part = c - row * CPR;
                     const bool rho_row = row >= prow;
