@@ -513,36 +513,73 @@ __device__ __forceinline__ void inv_x_tile(const XGeom& g, const c2<TC>* __restr
     C* tw = xb + inv_x_stage_span(M, g.lb);
     const size_t plane_s = (size_t)g.mx * g.ny;
     const int nin = (M + 1) * g.lb;
-    // one index space: the lb lines' M + 1 bins, then the 2 M twiddles
     const c2<TS>* sk = spec + (size_t)k * plane_s + j0;
-    block_copy<4, C>(
-        nin + 2 * M,
-        [&](int t) {
-            const int m = t / g.lb;
-            return t < nin ? cconv<C>(sk[(size_t)m * g.ny + (t - m * g.lb)]) : tw_g[t - nin];
-        },
-        [&](int t, C x) {
-            if (t < nin) {
+    // Both branches stage the bins and the twiddles, then split the
+    // half-length transform's input: Z_m = E_m + i O_m with
+    // E_m = (X_m + conj X_{M-m}) / 2, O_m = (X_m - conj X_{M-m}) exp(+2 pi i m / nx) / 2,
+    // m = 0..M-1.
+    // FP64 compile-time lengths: the bins (in their load order t = m lb +
+    // line) and the twiddles by direct-to-LDS loads, 64 entries per wave
+    // instruction; the split reads bin m of line l at xb[m lb + l] and clears
+    // the imaginary parts of the DC and Nyquist bins itself.
+    constexpr bool DMA = std::is_same<TC, double>::value && std::is_same<TS, double>::value && N > 0;
+    if constexpr (DMA) {
+        const int lane = (int)threadIdx.x & 63;
+        const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+        const int cin = (nin + 63) / 64, nch = cin + (2 * M + 63) / 64;
+        for (int c = wave; c < nch; c += 4) {
+            if (c < cin) {
+                const int t = c * 64 + lane;
                 const int m = t / g.lb;
-                if (m == 0 || m == M) x.y = (TC)0;  // a real field has real DC and Nyquist bins
-                xb[(t - m * g.lb) * (M + 1) + m] = x;
+                if (t < nin) lds_dma16(sk + (size_t)m * g.ny + (t - m * g.lb), xb + c * 64);
             } else {
-                tw[t - nin] = x;
+                const int e = (c - cin) * 64;
+                if (e + lane < 2 * M) lds_dma16(tw_g + e + lane, tw + e);
             }
-        });
-    __syncthreads();
-    // Z_m = E_m + i O_m with E_m = (X_m + conj X_{M-m}) / 2 and
-    // O_m = (X_m - conj X_{M-m}) exp(+2 pi i m / nx) / 2, m = 0..M-1.
-    const int nzz = M * g.lb;
-    for (int t = threadIdx.x; t < nzz; t += 256) {
-        const int line = t / M;
-        const int m = t - line * M;
-        const C xm = xb[line * (M + 1) + m];
-        const C xc = cconj(xb[line * (M + 1) + (M - m)]);
-        const C e = C{(TC)0.5 * (xm.x + xc.x), (TC)0.5 * (xm.y + xc.y)};
-        const C d = C{(TC)0.5 * (xm.x - xc.x), (TC)0.5 * (xm.y - xc.y)};
-        const C o = cmul(d, cconj(tw[m]));
-        buf0[P::at(line * M + m)] = C{e.x - o.y, e.y + o.x};
+        }
+        lds_dma_wait();
+        __syncthreads();
+        const int nzz = M * g.lb;
+        for (int t = threadIdx.x; t < nzz; t += 256) {
+            const int line = t / M;
+            const int m = t - line * M;
+            C xm = xb[m * g.lb + line];
+            C xc = cconj(xb[(M - m) * g.lb + line]);
+            if (m == 0) xm.y = xc.y = (TC)0;  // real DC (m = 0) and Nyquist (M - m = M) bins
+            const C e = C{(TC)0.5 * (xm.x + xc.x), (TC)0.5 * (xm.y + xc.y)};
+            const C d = C{(TC)0.5 * (xm.x - xc.x), (TC)0.5 * (xm.y - xc.y)};
+            const C o = cmul(d, cconj(tw[m]));
+            buf0[P::at(line * M + m)] = C{e.x - o.y, e.y + o.x};
+        }
+    } else {
+        // one index space: the lb lines' M + 1 bins, then the 2 M twiddles
+        block_copy<4, C>(
+            nin + 2 * M,
+            [&](int t) {
+                const int m = t / g.lb;
+                return t < nin ? cconv<C>(sk[(size_t)m * g.ny + (t - m * g.lb)]) : tw_g[t - nin];
+            },
+            [&](int t, C x) {
+                if (t < nin) {
+                    const int m = t / g.lb;
+                    if (m == 0 || m == M) x.y = (TC)0;  // a real field has real DC and Nyquist bins
+                    xb[(t - m * g.lb) * (M + 1) + m] = x;
+                } else {
+                    tw[t - nin] = x;
+                }
+            });
+        __syncthreads();
+        const int nzz = M * g.lb;
+        for (int t = threadIdx.x; t < nzz; t += 256) {
+            const int line = t / M;
+            const int m = t - line * M;
+            const C xm = xb[line * (M + 1) + m];
+            const C xc = cconj(xb[line * (M + 1) + (M - m)]);
+            const C e = C{(TC)0.5 * (xm.x + xc.x), (TC)0.5 * (xm.y + xc.y)};
+            const C d = C{(TC)0.5 * (xm.x - xc.x), (TC)0.5 * (xm.y - xc.y)};
+            const C o = cmul(d, cconj(tw[m]));
+            buf0[P::at(line * M + m)] = C{e.x - o.y, e.y + o.x};
+        }
     }
     __syncthreads();
     C* z = lds_fft_n<N, +1, 2, P>(buf0, xb, M, g.lb, M, g.rad, tw);
