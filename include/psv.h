@@ -287,7 +287,7 @@ psv_status psv_solve_converged_adjoint(psv_plan* plan, const double* w, const do
  * with autotune = 0), without info. opts may be NULL (defaults); it must have
  * precision PSV_FP64, autotune 0 and check_inputs 0 (PSV_ERR_INVALID_ARG);
  * chunk_rows and x_stencil are honoured. Tables and workspace must fit the
- * array (about 5 million cells; 128^3 takes 25 MB of it):
+ * array (about 5 million cells; 128^3 takes about 24 MB of it):
  * PSV_ERR_UNSUPPORTED_SIZE otherwise, before any device work when the
  * spectrum alone is too large. Every call on one GPU shares that GPU's array:
  * calls that overlap in time on one GPU (other streams, other threads) race
