@@ -285,11 +285,15 @@ def test_misaligned_field_pointers_rejected(gpu):
 # lines and the FP64 residual of the mixed refinement. Without staging the x
 # neighbours come by lane exchange for half-lengths 16, 32, 64 (groups of
 # lanes, one line per group), 128 and 512 (64 pairs of a line per wave, edge
-# lanes load theirs) and by loads for 48 and the runtime lengths.
+# lanes load theirs) and by loads for 48 and the runtime lengths. The FP64
+# staged rows, bins and twiddles of compile-time lengths arrive by
+# direct-to-LDS loads in 64-entry chunks: half-lengths 48, 96 and 192 end
+# each row with a partial chunk.
 @pytest.mark.parametrize("shape,stretched", [((12, 18, 10), True), ((32, 48, 17), False),
                                              ((64, 1, 40), True), ((1024, 6, 5), True),
                                              ((8, 6, 2), False), ((128, 4, 6), True),
-                                             ((256, 6, 5), False), ((96, 6, 5), True)])
+                                             ((256, 6, 5), False), ((96, 6, 5), True),
+                                             ((192, 6, 7), True), ((384, 6, 4), False)])
 @pytest.mark.parametrize("x_stencil", ["staged", "direct"])
 def test_x_stencil_variants(gpu, shape, stretched, x_stencil):
     nx, ny, nz = shape
