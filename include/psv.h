@@ -138,6 +138,10 @@ typedef struct {
     int32_t lines_x_inv;    /* x lines per block of the inverse x pass (divides ny) */
     int32_t chunk_rows;     /* rows per chunk of the wall-normal partition: 4, 8 or 16 */
     int32_t x_staged;       /* forward x pass: 1 stencil rows staged in LDS, 0 loaded directly */
+    int32_t x_order;        /* forward x pass tile order: 1 each XCD takes a window of lines
+                               through all planes (where the tiles per plane, ny / lines_x, are a
+                               multiple of 8; plane ranges otherwise), 0 each XCD takes a
+                               contiguous range of planes */
 } psv_shape;
 /* psv_plan_get_shape reads the shape the plan runs with; psv_plan_set_shape
  * replaces it (host-side checks first: PSV_ERR_INVALID_ARG for a field out of

@@ -43,7 +43,7 @@ class psv_info(C.Structure):
 
 class psv_shape(C.Structure):
     _fields_ = [("lines_x", C.c_int32), ("lines_x_inv", C.c_int32), ("chunk_rows", C.c_int32),
-                ("x_staged", C.c_int32)]
+                ("x_staged", C.c_int32), ("x_order", C.c_int32)]
 
 
 class psv_m3_info(C.Structure):

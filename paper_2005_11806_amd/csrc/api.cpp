@@ -217,6 +217,7 @@ psv_status psv_plan_get_shape(const psv_plan* plan, psv_shape* shape) {
         shape->lines_x_inv = l.lbx_inv;
         shape->chunk_rows = l.kc;
         shape->x_staged = l.xstage;
+        shape->x_order = l.xorder;
     });
 }
 
@@ -229,6 +230,7 @@ psv_status psv_plan_set_shape(psv_plan* plan, const psv_shape* shape) {
             need(lb >= 1 && lb <= 64 && P.ny % lb == 0, "lines per x block must divide ny (1..64)");
         need(h.chunk_rows == 4 || h.chunk_rows == 8 || h.chunk_rows == 16, "chunk_rows must be 4, 8 or 16");
         need(h.x_staged == 0 || h.x_staged == 1, "x_staged must be 0 or 1");
+        need(h.x_order == 0 || h.x_order == 1, "x_order must be 0 or 1");
         if (!psv::kc_fits(P, h.chunk_rows))
             psv::fail(PSV_ERR_UNSUPPORTED_SIZE, "the y tile of chunk_rows planes exceeds the LDS of a block");
         for (int lb : {h.lines_x, h.lines_x_inv})
@@ -238,6 +240,7 @@ psv_status psv_plan_set_shape(psv_plan* plan, const psv_shape* shape) {
         l.lbx = h.lines_x;
         l.lbx_inv = h.lines_x_inv;
         l.xstage = h.x_staged;
+        l.xorder = h.x_order;
         PSV_HIP(hipSetDevice(P.device));
         if (h.chunk_rows != P.lp.kc) psv::plan_set_kc(P, h.chunk_rows);
         l.kc = P.lp.kc;

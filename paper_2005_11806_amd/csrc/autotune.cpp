@@ -6,10 +6,14 @@
 // solve must match the default-shape solve (FP64: 1e-10, FP32 spectra: 1e-3
 // relative in the max norm) or the defaults stay. Choices are cached per
 // (arch, grid, precision, method) in the process and, when PSV_AUTOTUNE_CACHE
-// names a file, on disk (one "key lbx kc lbx_inv xstage" line per entry; the
-// last two may be missing). psv_opts.autotune = 1 only looks the plan up in
-// the cache (built-in shapes when it has no entry); 2 also times the
-// candidates when it has none and adds the choice to the cache.
+// names a file, on disk (one "key lbx kc lbx_inv xstage xorder" line per
+// entry; the last three may be missing). The forward pass's tile order
+// (xorder) is not timed: line windows measured faster than plane ranges
+// wherever the tiles split over the 8 XCDs (256x256x512: 240 against 250 us
+// in the same process), by less than the spread of the tuner's short
+// trials. psv_opts.autotune = 1 only looks the plan up in the cache
+// (built-in shapes when it has no entry); 2 also times the candidates when it
+// has none and adds the choice to the cache.
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -55,12 +59,17 @@ void load_cache() {
         std::string key, extra;
         Launch l;
         if (!(ls >> key >> l.lbx >> l.kc)) continue;
-        // entries may omit the inverse lines per block and the staging choice
+        // entries may omit the inverse lines per block, the staging choice
+        // and the tile order
         if (!(ls >> l.lbx_inv)) {
             l.lbx_inv = l.lbx;
         } else if (!(ls >> l.xstage)) {
             l.xstage = 1;
-        } else if (ls >> extra || (l.xstage != 0 && l.xstage != 1)) {
+        } else if (l.xstage != 0 && l.xstage != 1) {
+            continue;
+        } else if (!(ls >> l.xorder)) {
+            l.xorder = 1;
+        } else if (ls >> extra || (l.xorder != 0 && l.xorder != 1)) {
             continue;
         }
         g_cache[key] = l;
@@ -72,7 +81,8 @@ void store_cache(const std::string& key, const Launch& l) {
     const char* path = std::getenv("PSV_AUTOTUNE_CACHE");
     if (!path) return;
     std::ofstream out(path, std::ios::app);
-    out << key << " " << l.lbx << " " << l.kc << " " << l.lbx_inv << " " << l.xstage << "\n";
+    out << key << " " << l.lbx << " " << l.kc << " " << l.lbx_inv << " " << l.xstage << " "
+        << l.xorder << "\n";
 }
 
 // deterministic synthetic inputs: f, p_prev smooth-ish, rho in [1, 1000]
@@ -141,6 +151,7 @@ void autotune_plan(Plan& p) {
             p.lp.lbx_inv = it->second.lbx_inv;
             // a stencil variant fixed by the caller wins over the cached one
             if (!p.opts.x_stencil) p.lp.xstage = it->second.xstage;
+            p.lp.xorder = it->second.xorder;
             if (!kc_fixed && it->second.kc != p.lp.kc) plan_set_kc(p, it->second.kc);
             return;
         }
@@ -220,8 +231,8 @@ void autotune_plan(Plan& p) {
         p.lp = def;
         plan_set_kc(p, def.kc);
     } else if (std::getenv("PSV_LOG")) {
-        std::fprintf(stderr, "psv autotune: %s -> lbx %d kc %d lbx_inv %d xstage %d\n", key.c_str(),
-                     p.lp.lbx, p.lp.kc, p.lp.lbx_inv, p.lp.xstage);
+        std::fprintf(stderr, "psv autotune: %s -> lbx %d kc %d lbx_inv %d xstage %d xorder %d\n",
+                     key.c_str(), p.lp.lbx, p.lp.kc, p.lp.lbx_inv, p.lp.xstage, p.lp.xorder);
     }
     store_cache(key, p.lp);
     (void)hipStreamDestroy(s);

@@ -407,4 +407,17 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
     return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + i;
 }
 
+// Forward x tiles in line windows: XCD x takes tiles x w .. x w + w - 1 of
+// every plane (w = tiles per plane / 8), plane after plane. The z
+// neighbours a tile reads are then the rows of the tiles just before and
+// after it in the same XCD's sweep, fetched at about the same time, and the
+// y neighbours come from another XCD only at the window's two edges. (With
+// contiguous plane ranges an XCD works on about two planes at once and the
+// neighbouring planes of p and rho leave its L2 between their uses.)
+__device__ __forceinline__ int xcd_windows(int b, int w, int tiles) {
+    const int x = b & 7, i = b >> 3;
+    const int k = i / w;
+    return k * tiles + x * w + (i - k * w);
+}
+
 }  // namespace psv

@@ -97,6 +97,7 @@ struct Launch {
     int kc = 8;       // planes per y tile = rows per chunk of the z partition
     int lbx_inv = 8;  // lines per block, inverse x pass of a plan
     int xstage = 1;   // forward x pass of a plan: stencil rows staged in LDS (1) or read directly (0)
+    int xorder = 1;   // forward x pass of a plan: tiles in line windows (1) or plane ranges (0) per XCD
 };
 
 // Launch-shape autotuning (autotune.cpp): times candidate shapes per pass on

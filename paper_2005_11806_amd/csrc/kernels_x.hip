@@ -1,5 +1,6 @@
 // Per-pass kernels of the x direction (tile bodies in pass_x.hpp): one block
-// per tile, remapped so each XCD walks a contiguous range of planes.
+// per tile, remapped so each XCD walks a contiguous range of tiles (of planes,
+// or for the forward pass of lines through all planes).
 #include "pass_x.hpp"
 
 namespace psv {
@@ -12,8 +13,8 @@ __global__ void __launch_bounds__(256) k_fwd_x(XGeom g, Stencil st, FwdArgs a,
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ double red[16];
     if (a.done && *a.done) return;
-    fwd_x_tile<TC, TS, MODE, N, STAGE>(g, st, a, tw_g, spec, xcd_remap(blockIdx.x, gridDim.x),
-                                       smem_raw, red);
+    const int b = g.win ? xcd_windows(blockIdx.x, g.win, g.tiles) : xcd_remap(blockIdx.x, gridDim.x);
+    fwd_x_tile<TC, TS, MODE, N, STAGE>(g, st, a, tw_g, spec, b, smem_raw, red);
 }
 
 template <typename TC, typename TS, int MODE, int N>

@@ -18,6 +18,7 @@ namespace psv {
 struct XGeom {
     int nx, ny, nz, mx, M, lb, tiles;  // tiles = ny / lb
     int stage;                         // forward tile: stencil rows staged in LDS (1) or not (0)
+    int win;                           // forward pass: tiles per XCD line window, 0 = plane ranges
     double inv_dx, inv_dy;
     Radices rad;
 };
@@ -613,6 +614,7 @@ inline XGeom make_xgeom(const Plan& p, bool inverse = false) {
     g.lb = inverse ? p.lp.lbx_inv : p.lp.lbx;
     g.tiles = p.ny / g.lb;
     g.stage = p.lp.xstage;
+    g.win = (!inverse && p.lp.xorder && g.tiles % 8 == 0) ? g.tiles / 8 : 0;
     g.inv_dx = 1.0 / p.dx;
     g.inv_dy = 1.0 / p.dy;
     g.rad = p.rad_xh;

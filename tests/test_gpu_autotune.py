@@ -33,9 +33,10 @@ def test_autotuned_plan_matches_default(gpu, precision, tmp_path, monkeypatch):
 
 
 def test_cache_entries_of_every_format(tmp_path):
-    """Cache lines written with 3, 4 or 5 fields (lines per block, chunk rows,
-    then optionally the inverse pass's lines per block and the stencil
-    choice) are all honoured; a fresh process reads them."""
+    """Cache lines written with 3 to 6 fields (lines per block, chunk rows,
+    then optionally the inverse pass's lines per block, the stencil choice
+    and the forward tile order) are all honoured; a fresh process reads
+    them. Missing choices take the built-in ones (staged rows, line windows)."""
     import json
     import subprocess
     import sys
@@ -44,16 +45,17 @@ def test_cache_entries_of_every_format(tmp_path):
     cache = tmp_path / "tune.txt"
     cache.write_text(f"{arch}:32x32x24:fp64:method1 2 4\n"
                      f"{arch}:48x32x24:fp64:method1 4 8 2\n"
-                     f"{arch}:64x32x24:fp64:method1 8 4 2 0\n")
+                     f"{arch}:64x32x24:fp64:method1 8 4 2 0\n"
+                     f"{arch}:96x32x24:fp64:method1 4 8 2 1 0\n")
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
     script = (
         "import json, sys\n"
         f"sys.path.insert(0, {root!r})\n"
         "import paper_2005_11806_amd as psv\n"
         "out = {}\n"
-        "for nx in (32, 48, 64):\n"
+        "for nx in (32, 48, 64, 96):\n"
         "    plan = psv.Plan(psv.Grid(nx, 32, 24, 1.0, 1.0, 1.0), autotune=1)\n"
-        "    out[nx] = plan.launch_shape()\n"
+        "    out[nx] = plan.get_shape()\n"
         "print(json.dumps(out))\n")
     env = dict(os.environ, PSV_AUTOTUNE_CACHE=str(cache))
     res = subprocess.run([sys.executable, "-c", script], env=env, capture_output=True, text=True,
@@ -61,7 +63,10 @@ def test_cache_entries_of_every_format(tmp_path):
     assert res.returncode == 0, res.stderr[-2000:]
     shapes = json.loads(res.stdout.strip().splitlines()[-1])
     say(f"cached shapes {shapes}")
-    assert shapes == {"32": [2, 4], "48": [4, 8], "64": [8, 4]}
+    def sh(lx, kc, li, st, order):
+        return {"lines_x": lx, "lines_x_inv": li, "chunk_rows": kc, "x_staged": st, "x_order": order}
+    assert shapes == {"32": sh(2, 4, 2, 1, 1), "48": sh(4, 8, 2, 1, 1), "64": sh(8, 4, 2, 0, 1),
+                      "96": sh(4, 8, 2, 1, 0)}
 
 
 def test_cache_only_mode_never_times(gpu, tmp_path, monkeypatch):
@@ -92,12 +97,14 @@ def test_shape_api_round_trip_and_checks(gpu):
     g, f, rho, pp = oracle_inputs(case)
     plan = gpu.Plan(gpu.Grid.from_spec(spec))
     ref = host(plan.solve(dev(f), rho=dev(rho), p_prev=dev(pp)))
-    plan.set_shape(lines_x=8, lines_x_inv=4, chunk_rows=4, x_staged=0)
-    assert plan.get_shape() == {"lines_x": 8, "lines_x_inv": 4, "chunk_rows": 4, "x_staged": 0}
+    plan.set_shape(lines_x=8, lines_x_inv=4, chunk_rows=4, x_staged=0, x_order=0)
+    assert plan.get_shape() == {"lines_x": 8, "lines_x_inv": 4, "chunk_rows": 4, "x_staged": 0,
+                                "x_order": 0}
     assert plan.launch_shape() == (8, 4)
     p = host(plan.solve(dev(f), rho=dev(rho), p_prev=dev(pp)))
     assert rel_max_err(p, ref) <= 1e-12
-    for bad in ({"lines_x": 3}, {"lines_x_inv": 0}, {"chunk_rows": 5}, {"x_staged": 2}):
+    for bad in ({"lines_x": 3}, {"lines_x_inv": 0}, {"chunk_rows": 5}, {"x_staged": 2},
+                {"x_order": -1}):
         with pytest.raises(gpu.PsvError):
             plan.set_shape(**bad)
     assert plan.get_shape()["lines_x"] == 8  # a rejected call changes nothing
