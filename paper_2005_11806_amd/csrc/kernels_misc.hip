@@ -57,7 +57,7 @@ __global__ void __launch_bounds__(RB) k_min_partial(const double* __restrict__ x
     for (; c + (U - 1) * RB < c1; c += U * RB) {
         double2 v[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) v[u] = x2[c + u * RB];
+        for (int u = 0; u < U; ++u) v[u] = ld_stream(x2 + c + u * RB);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             if (v[u].x < best) { best = v[u].x; bi = (int)(2 * (c + u * RB)); }
@@ -65,7 +65,7 @@ __global__ void __launch_bounds__(RB) k_min_partial(const double* __restrict__ x
         }
     }
     for (; c < c1; c += RB) {
-        const double2 v = x2[c];
+        const double2 v = ld_stream(x2 + c);
         if (v.x < best) { best = v.x; bi = (int)(2 * c); }
         if (v.y < best) { best = v.y; bi = (int)(2 * c + 1); }
     }

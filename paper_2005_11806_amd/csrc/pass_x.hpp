@@ -225,17 +225,18 @@ __device__ __forceinline__ void fwd_x_tile(const XGeom& g, const Stencil& st, co
     Pre cur[PF];
     prefetch(threadIdx.x, cur);
     // The twiddles and (with STAGE) the rows j0-1 .. j0+lb of p and rho
-    // (periodic in y; p reads as 0 without an iterate) go to LDS. FP64
-    // compile-time lengths: by direct-to-LDS loads, in 64-entry chunks (one
-    // per wave instruction), the waves taking every fourth chunk; nothing
-    // passes through registers. Otherwise through registers, every load of a
-    // thread issued before its LDS writes: a p element and the rho element at
-    // the same place share their address, and the twiddles of compile-time
-    // lengths wait in registers.
+    // (periodic in y; p reads as 0 without an iterate) go to LDS. Compile-time
+    // lengths: the rows (FP64 at either spectrum precision) and FP64 twiddles
+    // by direct-to-LDS loads, in 64-entry chunks (one per wave instruction),
+    // the waves taking every fourth chunk, nothing passing through registers;
+    // FP32 twiddles (8-byte entries whose LDS slot is only 8-byte aligned)
+    // wait in registers meanwhile. Runtime lengths: through registers, every
+    // load of a thread issued before its LDS writes (a p element and the rho
+    // element at the same place share their address).
     {
         constexpr bool ROWS = MODE != FWD_CONST && STAGE;
         constexpr bool RHO = MODE == FWD_METHOD1 || MODE == FWD_METHOD3;
-        constexpr bool DMA = std::is_same<TC, double>::value && N > 0;
+        constexpr bool DMA = N > 0;
         const int nst = ROWS ? (lb + 2) * M : 0;
         const size_t kbase = (size_t)k * g.ny * M;
         auto row_j = [&](int rr) {
@@ -245,8 +246,18 @@ __device__ __forceinline__ void fwd_x_tile(const XGeom& g, const Stencil& st, co
             return j;
         };
         if constexpr (DMA) {
-            constexpr int CPR = (N + 63) / 64;        // chunks per row
-            constexpr int CTW = (2 * N + 63) / 64;    // chunks of twiddles
+            constexpr bool TWD = std::is_same<TC, double>::value;  // twiddles by direct loads
+            constexpr int TWP = (2 * N + 255) / 256;
+            C twr[TWD ? 1 : TWP];
+            if constexpr (!TWD) {
+#pragma unroll
+                for (int j = 0; j < TWP; ++j) {
+                    const int t = (int)threadIdx.x + 256 * j;
+                    twr[j] = tw_g[t < 2 * N ? t : 0];
+                }
+            }
+            constexpr int CPR = (N + 63) / 64;                 // chunks per row
+            constexpr int CTW = TWD ? (2 * N + 63) / 64 : 0;  // chunks of twiddles
             const int prow = ROWS && has_p ? lb + 2 : 0;
             const int nrow = prow + (ROWS && RHO ? lb + 2 : 0);
             const int nch = nrow * CPR + CTW;
@@ -261,9 +272,16 @@ __device__ __forceinline__ void fwd_x_tile(const XGeom& g, const Stencil& st, co
                     const size_t sb = kbase + (size_t)row_j(rr) * M + part * 64;
                     double2* dst = (rho_row ? rt : pt) + rr * M + part * 64;
                     if (part * 64 + lane < M) lds_dma16((rho_row ? rg : pg) + sb + lane, dst);
-                } else {
+                } else if constexpr (TWD) {
                     const int e = (c - nrow * CPR) * 64;
                     if (e + lane < 2 * M) lds_dma16(tw_g + e + lane, tw + e);
+                }
+            }
+            if constexpr (!TWD) {
+#pragma unroll
+                for (int j = 0; j < TWP; ++j) {
+                    const int t = (int)threadIdx.x + 256 * j;
+                    if (t < 2 * N) tw[t] = twr[j];
                 }
             }
             if (ROWS && !has_p)
@@ -599,7 +617,7 @@ __device__ __forceinline__ void inv_x_tile(const XGeom& g, const c2<TC>* __restr
             x.x += o.x;
             x.y += o.y;
         }
-        out2[c2] = x;
+        st_stream(out2 + c2, x);
     }
 }
 

@@ -479,7 +479,7 @@ __device__ __forceinline__ void ifc_scan(const ZArgs& z, c2<T>* __restrict__ spe
         const bool rhs = row && ifc_plane(z, r) < z.nz;
         const T* tj = tw + (size_t)(j < Q ? j : 0) * 3 * 64;
         const unsigned od = rhs ? (unsigned)ifc_plane(z, r) * uS + us : s0;
-        const T A = tj[0], Cc = tj[64], I = tj[128];
+        const T A = ld_stream(tj), Cc = ld_stream(tj + 64), I = ld_stream(tj + 128);
         const C D = spec[od];
         al[j] = row ? A : (T)1;
         cm[j] = row ? Cc : (T)1;
