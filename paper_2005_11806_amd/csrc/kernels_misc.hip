@@ -421,9 +421,16 @@ __global__ void __launch_bounds__(RB) k_adjoint_faces(Geo g, AdjArgs a) {
     const double2* RH = reinterpret_cast<const double2*>(a.rho);
     const double2* P = reinterpret_cast<const double2*>(a.pp);
     double acc = 0.0;
-    // one block per RB consecutive pairs, each XCD on a contiguous range (the
-    // y and z neighbours of its pairs were loaded into its own L2)
-    const unsigned bx = (unsigned)xcd_remap((int)blockIdx.x, (int)gridDim.x);
+    // one block per RB consecutive pairs. Where a plane is a whole number of
+    // blocks, a multiple of 8, and every pair has its own block, each XCD
+    // takes a window of 1/8 of every plane's blocks, plane after plane (the
+    // z neighbours of a block's pairs are then the pairs of the blocks just
+    // before and after it in the same XCD's sweep); else each XCD takes a
+    // contiguous range
+    const unsigned tpp = plane2 / RB;  // blocks per plane
+    const bool win = plane2 % RB == 0 && tpp % 8 == 0 && gridDim.x * RB == npair;
+    const unsigned bx = win ? (unsigned)xcd_windows((int)blockIdx.x, (int)(tpp / 8), (int)tpp)
+                            : (unsigned)xcd_remap((int)blockIdx.x, (int)gridDim.x);
     // x neighbours from the adjacent lanes where a wave holds whole lines (M
     // divides 64) or 64 pairs of one line (64 divides M; the wave's first and
     // last lanes load theirs); whole lane groups are active together
@@ -535,9 +542,10 @@ __global__ void __launch_bounds__(RB) k_adjoint_faces(Geo g, AdjArgs a) {
             const double2 fc = reinterpret_cast<const double2*>(a.f)[q];
             acc += m0 * fc.x + m1 * fc.y;
         }
-        if (a.grad_f) reinterpret_cast<double2*>(a.grad_f)[q] = double2{rho0 * m0, rho0 * m1};
-        if (a.grad_rho) reinterpret_cast<double2*>(a.grad_rho)[q] = double2{gr0, gr1};
-        if (a.grad_p) reinterpret_cast<double2*>(a.grad_p)[q] = double2{gp0, gp1};
+        // the gradients are outputs no later pass reads: streaming stores
+        if (a.grad_f) st_stream(reinterpret_cast<double2*>(a.grad_f) + q, double2{rho0 * m0, rho0 * m1});
+        if (a.grad_rho) st_stream(reinterpret_cast<double2*>(a.grad_rho) + q, double2{gr0, gr1});
+        if (a.grad_p) st_stream(reinterpret_cast<double2*>(a.grad_p) + q, double2{gp0, gp1});
     }
     const double s = block_sum(acc, sh);
     if (threadIdx.x == 0) a.partials[blockIdx.x] = s;
