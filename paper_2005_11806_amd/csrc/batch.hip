@@ -139,9 +139,7 @@ __device__ void minf_tile(const ProblemDesc& D, const ProblemIO& io) {
 
 // sum of `per` interleaved partials over nb tiles, on thread 0
 __device__ double sum_partials(const double* p, int nb, int per, int q, double* red) {
-    double v = 0.0;
-    for (int b = threadIdx.x; b < nb; b += 256) v += p[(size_t)per * b + q];
-    return block_sum(v, red);
+    return block_sum(thread_share(p, nb, per, q), red);
 }
 
 __device__ void mean_tile(const ProblemDesc& D, double* red) {
@@ -150,9 +148,10 @@ __device__ void mean_tile(const ProblemDesc& D, double* red) {
 }
 
 __device__ void nrm_tile(const ProblemDesc& D, int ntiles, double* red, bool set_done) {
-    const double a = sum_partials(D.partials, ntiles, 2, 0, red);
+    const double2 ab = thread_share2(D.partials, ntiles);
+    const double a = block_sum(ab.x, red);
     __syncthreads();
-    const double b = sum_partials(D.partials, ntiles, 2, 1, red);
+    const double b = block_sum(ab.y, red);
     if (threadIdx.x == 0) {
         const double rr = b > 0.0 ? sqrt(a / b) : 0.0;
         D.scal[S_RELRES] = rr;

@@ -379,6 +379,50 @@ __device__ __forceinline__ void block_copy(int n, Get&& get, Put&& put) {
 __device__ __forceinline__ void lds_dma16(const void* src, void* lds_base) {
     __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)lds_base, 16, 0, 0);
 }
+// This thread's share of sum_b p[stride b + off] over b < nb (b = thread +
+// 256 i, in a block of 256 threads), with U loads in flight per round: a
+// plain loop waits for each load in turn, which took a single block 50 us
+// over the 32768 partials of a 256x256x512 forward pass. The order of the
+// additions is fixed.
+__device__ __forceinline__ double thread_share(const double* p, int nb, int stride, int off) {
+    constexpr int U = 16;
+    double acc[U] = {};
+    int b = threadIdx.x;
+    for (; b + (U - 1) * 256 < nb; b += U * 256) {
+        double v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = p[(size_t)stride * (b + u * 256) + off];
+#pragma unroll
+        for (int u = 0; u < U; ++u) acc[u] += v[u];
+    }
+    for (; b < nb; b += 256) acc[0] += p[(size_t)stride * b + off];
+#pragma unroll
+    for (int h = U / 2; h > 0; h /= 2)
+#pragma unroll
+        for (int u = 0; u < h; ++u) acc[u] += acc[u + h];
+    return acc[0];
+}
+// The same for two interleaved sums (p[2 b], p[2 b + 1]) in one pass.
+__device__ __forceinline__ double2 thread_share2(const double* p, int nb) {
+    constexpr int U = 16;
+    const double2* p2 = reinterpret_cast<const double2*>(p);
+    double2 acc[U] = {};
+    int b = threadIdx.x;
+    for (; b + (U - 1) * 256 < nb; b += U * 256) {
+        double2 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = p2[b + u * 256];
+#pragma unroll
+        for (int u = 0; u < U; ++u) acc[u] = double2{acc[u].x + v[u].x, acc[u].y + v[u].y};
+    }
+    for (; b < nb; b += 256) acc[0] = double2{acc[0].x + p2[b].x, acc[0].y + p2[b].y};
+#pragma unroll
+    for (int h = U / 2; h > 0; h /= 2)
+#pragma unroll
+        for (int u = 0; u < h; ++u) acc[u] = double2{acc[u].x + acc[u + h].x, acc[u].y + acc[u + h].y};
+    return acc[0];
+}
+
 // Non-temporal (streaming) accesses, for data that no later pass of the
 // solve reads from the caches: the solution p (written last), the density
 // as the min reduction reads it, and the interface factor table. On the

@@ -5,6 +5,7 @@
 // Reductions are two-stage (per-block partials, then one block) so that
 // their results do not depend on scheduling.
 #include <algorithm>
+#include <cstdint>
 
 #include "internal.hpp"
 
@@ -140,14 +141,47 @@ __global__ void __launch_bounds__(RB) k_harmonic_final(const double* pv, int nb,
     }
 }
 
+// First stage of a sum over a long partial array: block i of the grid sums
+// its contiguous share of the nb entries of each of the `per` interleaved
+// sums (per <= 2) into out[per i + q]. One block reading all 32768 partials
+// of a 256x256x512 forward pass waits on memory round after round (25-50
+// us); split over STAGE1_BLOCKS blocks it does not. Skipped when *done.
+constexpr int STAGE1_BLOCKS = 32;
+__global__ void __launch_bounds__(RB) k_partials_stage1(const double* partials, int nb, int per,
+                                                        double* out, const int* done) {
+    __shared__ double sh[16];
+    if (done && *done) return;
+    const int b0 = (int)((long long)nb * blockIdx.x / gridDim.x);
+    const int b1 = (int)((long long)nb * (blockIdx.x + 1) / gridDim.x);
+    auto at = [&](int b, int q) { return partials[(size_t)per * b + q]; };
+    for (int q = 0; q < per; ++q) {
+        double v = 0.0;
+        int b = b0 + (int)threadIdx.x;
+        for (; b + 3 * RB < b1; b += 4 * RB) {  // four loads in flight
+            const double t0 = at(b, q), t1 = at(b + RB, q), t2 = at(b + 2 * RB, q), t3 = at(b + 3 * RB, q);
+            v += (t0 + t1) + (t2 + t3);
+        }
+        for (; b < b1; b += RB) v += at(b, q);
+        const double t = block_sum(v, sh);
+        if (threadIdx.x == 0) out[per * blockIdx.x + q] = t;
+    }
+}
+
 // Sum of `per` interleaved partial sums over nb blocks.
 __global__ void __launch_bounds__(RB) k_sum_partials(const double* partials, int nb, int per,
                                                      double* out) {
     __shared__ double sh[16];
+    if (per == 2) {  // both sums in one pass over the pairs
+        const double2 ab = thread_share2(partials, nb);
+        const double a = block_sum(ab.x, sh);
+        if (threadIdx.x == 0) out[0] = a;
+        __syncthreads();
+        const double b = block_sum(ab.y, sh);
+        if (threadIdx.x == 0) out[1] = b;
+        return;
+    }
     for (int q = 0; q < per; ++q) {
-        double v = 0.0;
-        for (int b = threadIdx.x; b < nb; b += RB) v += partials[(size_t)per * b + q];
-        const double s = block_sum(v, sh);
+        const double s = block_sum(thread_share(partials, nb, per, q), sh);
         if (threadIdx.x == 0) out[q] = s;
         __syncthreads();
     }
@@ -177,14 +211,10 @@ __global__ void __launch_bounds__(RB) k_refine_check(const double* partials, int
                                                      int* flags) {
     __shared__ double sh[16];
     if (flags[F_DONE]) return;  // uniform over the block
-    double a = 0.0, b = 0.0;
-    for (int i = threadIdx.x; i < nb; i += RB) {
-        a += partials[2 * (size_t)i];
-        b += partials[2 * (size_t)i + 1];
-    }
-    a = block_sum(a, sh);
+    const double2 ab = thread_share2(partials, nb);
+    const double a = block_sum(ab.x, sh);
     __syncthreads();
-    b = block_sum(b, sh);
+    const double b = block_sum(ab.y, sh);
     if (threadIdx.x == 0) {
         const double rr = b > 0.0 ? sqrt(a / b) : 0.0;
         scal[S_RELRES] = rr;
@@ -213,9 +243,7 @@ __global__ void __launch_bounds__(RB) k_m3_check(const double* partials, int nb,
                                                  double* scal, int* flags) {
     __shared__ double sh[16];
     if (flags[F_DONE]) return;  // uniform over the block
-    double v = 0.0;
-    for (int b = threadIdx.x; b < nb; b += RB) v += partials[b];
-    const double eps = dt * block_sum(v, sh);
+    const double eps = dt * block_sum(thread_share(partials, nb, 1, 0), sh);
     if (threadIdx.x != 0) return;
     if (!has_p) {
         scal[S_EPS0] = eps;
@@ -642,8 +670,27 @@ void launch_harmonic_weight(const Plan& p, const double* rho, hipStream_t s) {
     PSV_HIP(hipGetLastError());
 }
 
+// Long partial arrays (more than 2048 entries per sum) first go through
+// k_partials_stage1 into the last 2 STAGE1_BLOCKS entries of the plan's
+// partials buffer. The x passes' arrays (one or two entries per tile) never
+// reach them, as the buffer holds at least 2 ny nz + 64 entries; a source
+// that spans them is read by the single block directly. Returns the array
+// the final single-block pass reads; nb becomes its length.
+const double* stage_partials(const Plan& p, const double* partials, int& nb, int per,
+                             const int* done, hipStream_t s) {
+    double* out = p.partials + (p.n_partials - 2 * STAGE1_BLOCKS);
+    const uintptr_t a0 = (uintptr_t)partials, a1 = (uintptr_t)(partials + (size_t)per * nb);
+    const uintptr_t o0 = (uintptr_t)out, o1 = (uintptr_t)(out + 2 * STAGE1_BLOCKS);
+    if (nb <= 2048 || per > 2 || (a0 < o1 && o0 < a1)) return partials;
+    hipLaunchKernelGGL(k_partials_stage1, dim3(STAGE1_BLOCKS), dim3(RB), 0, s, partials, nb, per,
+                       out, done);
+    nb = STAGE1_BLOCKS;
+    return out;
+}
+
 void launch_norm_finalize(const Plan& p, int nblocks, double tol, hipStream_t s) {
-    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(RB), 0, s, p.partials, nblocks, 2,
+    const double* src = stage_partials(p, p.partials, nblocks, 2, nullptr, s);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(RB), 0, s, src, nblocks, 2,
                        p.scal + S_RES2);
     hipLaunchKernelGGL(k_relres_final, dim3(1), dim3(64), 0, s, p.scal, p.flags, tol);
     PSV_HIP(hipGetLastError());
@@ -656,7 +703,8 @@ void launch_refine_reset(const Plan& p, hipStream_t s) {
 
 void launch_refine_check(const Plan& p, int nblocks, int sweep, int max_refine, double tol,
                          hipStream_t s) {
-    hipLaunchKernelGGL(k_refine_check, dim3(1), dim3(RB), 0, s, p.partials, nblocks, sweep,
+    const double* src = stage_partials(p, p.partials, nblocks, 2, p.flags + F_DONE, s);
+    hipLaunchKernelGGL(k_refine_check, dim3(1), dim3(RB), 0, s, src, nblocks, sweep,
                        max_refine, tol, p.scal, p.flags);
     PSV_HIP(hipGetLastError());
 }
@@ -714,14 +762,16 @@ void launch_m3_reset(const Plan& p, hipStream_t s) {
 
 void launch_m3_check(const Plan& p, const double* partials, int nblocks, double dt, double eps_t,
                      bool has_p, int max_iter, hipStream_t s) {
-    hipLaunchKernelGGL(k_m3_check, dim3(1), dim3(RB), 0, s, partials, nblocks, dt, eps_t,
+    const double* src = stage_partials(p, partials, nblocks, 1, p.flags + F_DONE, s);
+    hipLaunchKernelGGL(k_m3_check, dim3(1), dim3(RB), 0, s, src, nblocks, dt, eps_t,
                        has_p ? 1 : 0, max_iter, p.scal, p.flags);
     PSV_HIP(hipGetLastError());
 }
 
 void launch_sum_partials(const Plan& p, const double* partials, int nblocks, double* out,
                          hipStream_t s) {
-    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(RB), 0, s, partials, nblocks, 1, out);
+    const double* src = stage_partials(p, partials, nblocks, 1, nullptr, s);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(RB), 0, s, src, nblocks, 1, out);
     PSV_HIP(hipGetLastError());
 }
 
@@ -736,7 +786,8 @@ void launch_adjoint_faces(const Plan& p, const double* x, const double* f, const
 
 void launch_adjoint_finalize(const Plan& p, int nblocks, double* grad_rho, int add_argmin,
                              hipStream_t s) {
-    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(RB), 0, s, p.partials, nblocks, 1,
+    const double* src = stage_partials(p, p.partials, nblocks, 1, nullptr, s);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(RB), 0, s, src, nblocks, 1,
                        p.scal + S_GRAD_RHO0);
     if (add_argmin && grad_rho)
         hipLaunchKernelGGL(k_adjoint_argmin, dim3(1), dim3(64), 0, s, grad_rho, p.scal, p.flags);
@@ -761,7 +812,8 @@ void launch_vmean(const Plan& p, const double* r, double* out_scalar, hipStream_
 }
 
 void launch_mean_finalize(const Plan& p, int nblocks, double* out_scalar, hipStream_t s) {
-    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(RB), 0, s, p.partials, nblocks, 1, out_scalar);
+    const double* src = stage_partials(p, p.partials, nblocks, 1, nullptr, s);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(RB), 0, s, src, nblocks, 1, out_scalar);
     double total = 0.0;
     for (double h : p.h) total += h;
     hipLaunchKernelGGL(k_div_scalar, dim3(1), dim3(64), 0, s, out_scalar, p.dx * p.dy * total * p.nx * p.ny);
