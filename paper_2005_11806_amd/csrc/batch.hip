@@ -97,7 +97,7 @@ __device__ void minp_tile(const ProblemDesc& D, const ProblemIO& io, int b) {
     double best = __builtin_inf();
     int bi = 0x7fffffff;
     for (size_t c = c0 + threadIdx.x; c < c1; c += 256) {
-        const double v = io.rho[c];
+        const double v = ld_stream(io.rho + c);  // read once per solve: streaming
         if (v < best) { best = v; bi = (int)c; }
     }
     sv[threadIdx.x] = best;
