@@ -141,7 +141,12 @@ CoreResult solve_core(Plan& P, psv::FwdArgs a, double* out, bool want_relres, bo
     const int maxr = P.opts.max_refine;
     launch_refine_reset(P, s);
     res.have_relres = true;
+    // One refinement sweep usually converges: the x passes that follow its
+    // check (and, without host checks, return at once) run on a capped grid,
+    // as dispatching every tile's block costs more than the pass's early exit
+    constexpr int SPARE_BLOCKS = 1024;
     for (int sweep = 0;; ++sweep) {
+        ra.max_blocks = sweep >= 2 ? SPARE_BLOCKS : 0;
         launch_fwd_x(P, true, ra, s);
         launch_refine_check(P, fwd_x_blocks(P), sweep, maxr, P.opts.tol, s);
         if (host_checks) {
@@ -150,7 +155,7 @@ CoreResult solve_core(Plan& P, psv::FwdArgs a, double* out, bool want_relres, bo
         }
         if (sweep == maxr) break;
         launch_z_solve(P, true, P.scal + S_MEAN2, done, s);
-        launch_inv_x(P, true, INV_ADD, out, inv_scale, done, s);
+        launch_inv_x(P, true, INV_ADD, out, inv_scale, done, s, sweep >= 1 ? SPARE_BLOCKS : 0);
     }
     if (host_checks) {
         res.steps = P.host_flags[F_STEPS];

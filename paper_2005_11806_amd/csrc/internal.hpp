@@ -199,6 +199,7 @@ struct FwdArgs {
     double* partials;     // RESID: 2 per block
     double* partials_abs; // METHOD3: sum |f - D(rho_f^-1 G p)| per block
     const int* done;      // skip when *done != 0 (may be null)
+    int max_blocks;       // > 0: at most this many blocks (FP32 RESID only)
 };
 void launch_fwd_x(const Plan& p, bool fp32, const FwdArgs& a, hipStream_t s);
 // y passes with the chunk elimination (forward) or back substitution
@@ -215,8 +216,12 @@ void plan_set_kc(Plan& p, int kc);
 // fills p.ifc_tab for p.lp.kc on stream s.
 size_t ifc_table_bytes(const Plan& p, int kc);
 void launch_ifc_table(const Plan& p, hipStream_t s);
+// max_blocks > 0 (honoured by the FP32 INV_ADD pass): at most that many
+// blocks (a multiple of 8), each looping over tiles, for launches that
+// usually find *done set and return (a full grid still dispatches every
+// block)
 void launch_inv_x(const Plan& p, bool fp32, int mode, double* out, double scale_all,
-                  const int* done, hipStream_t s);
+                  const int* done, hipStream_t s, int max_blocks = 0);
 
 // Method II weight 2 a b / (a + b) of a = min rho, b = max rho into scal[S_OMEGA]
 // (also leaves them in scal[S_RHO0] and scal[S_RHOMAX]).

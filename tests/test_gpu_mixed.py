@@ -75,3 +75,24 @@ def test_mixed_solve_in_a_graph(gpu):
         assert rel_max_err(got, po) <= 1e-8
         assert torch.isfinite(junk).all()
     del graph
+
+
+def test_mixed_spare_sweeps_when_they_run(gpu):
+    """With a tolerance no sweep reaches, all max_refine sweeps run on the
+    device. The x passes after the first refinement run on a capped grid
+    (1024 blocks looping over 2304 tiles here, in line windows). The iterate
+    keeps improving: its residual against the oracle's right-hand side, with
+    the oracle's operator, ends at the FP64 floor, far below what one sweep
+    reaches (a tile left out would leave a residual of order 1)."""
+    case = _case((64, 128, 72), True, 83)
+    g, f, rho, pp = oracle_inputs(case)
+    plan = gpu.Plan(gpu.Grid.from_spec(case.grid), precision="mixed", tol=1e-30, max_refine=4)
+    plan.set_shape(lines_x=4, lines_x_inv=4, chunk_rows=8, x_staged=1, x_order=1)
+    p = host(plan.solve(dev(f), rho=dev(rho), p_prev=dev(pp)))  # device-checked sweeps
+    ps, r, _ = O.method1_step(f, rho, pp, float(rho.min()), g)
+    rr, _ = O.relres(r, p, g)
+    rr_oracle, _ = O.relres(r, ps, g)
+    say(f"4 sweeps on capped grids: relres {rr:.2e} (oracle's own {rr_oracle:.2e}), "
+        f"err vs oracle {rel_max_err(p, ps):.2e}")
+    assert rr <= max(1e-12, 10 * rr_oracle)
+    assert rel_max_err(p, ps) <= 1e-8
