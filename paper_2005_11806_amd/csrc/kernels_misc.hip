@@ -676,8 +676,8 @@ void launch_harmonic_weight(const Plan& p, const double* rho, hipStream_t s) {
 // reach them, as the buffer holds at least 2 ny nz + 64 entries; a source
 // that spans them is read by the single block directly. Returns the array
 // the final single-block pass reads; nb becomes its length.
-const double* stage_partials(const Plan& p, const double* partials, int& nb, int per,
-                             const int* done, hipStream_t s) {
+static const double* stage_partials(const Plan& p, const double* partials, int& nb, int per,
+                                    const int* done, hipStream_t s) {
     double* out = p.partials + (p.n_partials - 2 * STAGE1_BLOCKS);
     const uintptr_t a0 = (uintptr_t)partials, a1 = (uintptr_t)(partials + (size_t)per * nb);
     const uintptr_t o0 = (uintptr_t)out, o1 = (uintptr_t)(out + 2 * STAGE1_BLOCKS);
