@@ -81,7 +81,7 @@ inline int x_grid(int nt, int max_blocks) {
 template <typename TC, typename TS, int MODE, int N, bool STAGE>
 void fwd_launch_s(const Plan& p, const XGeom& g, const Stencil& st, const FwdArgs& a,
                   const c2<TC>* tw, hipStream_t s) {
-    const size_t lds = fwd_x_lds(g, sizeof(c2<TC>));
+    const size_t lds = fwd_x_lds(g, sizeof(c2<TC>), MODE);
     allow_lds(k_fwd_x<TC, TS, MODE, N, STAGE>, lds);
     const int nt = g.tiles * p.nz, grid = x_grid(nt, a.max_blocks);
     // capped grids only for the FP32 refinement residual, the one pass that

@@ -39,12 +39,13 @@ __host__ __device__ inline int xbuf_span(int n) { return n + (n >> 3) + 1; }
 
 // LDS bytes of the x tiles for complex element size csz. Forward: FFT buffer,
 // twiddles, then the second FFT buffer, which with `stage` shares its space
-// with the staged rows of p and rho (lb + 2 rows each, FP64) read by the
-// stencil before the transform. Inverse: FFT buffer, the staged half
-// spectrum (lb x (M+1), reused as the second FFT buffer), twiddles.
-inline size_t fwd_x_lds_n(int nx, int lb, size_t csz, bool stage = true) {
+// with the staged rows (lb + 2 rows, FP64) of the `fields` stencil fields:
+// p and rho (2), p alone for a residual (1), none for a copy (0). Inverse:
+// FFT buffer, the staged half spectrum (lb x (M+1), reused as the second
+// FFT buffer), twiddles.
+inline size_t fwd_x_lds_n(int nx, int lb, size_t csz, bool stage = true, int fields = 2) {
     const size_t M = nx / 2;
-    const size_t rows = stage ? (size_t)2 * (lb + 2) * nx * sizeof(double) : 0;
+    const size_t rows = stage ? (size_t)fields * (lb + 2) * nx * sizeof(double) : 0;
     const size_t buf = (size_t)xbuf_span(lb * (int)M) * csz;
     return buf + 2 * M * csz + 16 + (rows > buf ? rows : buf);
 }
@@ -56,7 +57,11 @@ inline size_t inv_x_lds_n(int nx, int lb, size_t csz) {
     const int M = nx / 2;
     return ((size_t)xbuf_span(lb * M) + inv_x_stage_span(M, lb) + 2 * (size_t)M) * csz;
 }
-inline size_t fwd_x_lds(const XGeom& g, size_t csz) { return fwd_x_lds_n(g.nx, g.lb, csz, g.stage != 0); }
+// mode: the forward pass's FwdMode (the default sizes for Method I, the most)
+inline size_t fwd_x_lds(const XGeom& g, size_t csz, int mode = FWD_METHOD1) {
+    const int fields = mode == FWD_CONST ? 0 : (mode == FWD_RESID ? 1 : 2);
+    return fwd_x_lds_n(g.nx, g.lb, csz, g.stage != 0, fields);
+}
 inline size_t inv_x_lds(const XGeom& g, size_t csz) { return inv_x_lds_n(g.nx, g.lb, csz); }
 // the larger of the two at FP64 (forward with staged rows), for choosing lines
 // per block
