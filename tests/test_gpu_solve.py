@@ -310,3 +310,26 @@ def test_x_stencil_variants(gpu, shape, stretched, x_stencil):
     mixed = gpu.Plan(gpu.Grid.from_spec(spec), precision="mixed", x_stencil=x_stencil)
     p, info = mixed.solve(dev(f), rho=dev(rho), p_prev=dev(pp), info=True)
     assert info.relres <= 1e-10 and rel_max_err(host(p), ps[0]) <= 1e-8
+
+
+# Forward x tile orders over the XCDs: line windows (each XCD takes 1/8 of
+# every plane's tiles, plane after plane) and contiguous plane ranges. Only
+# the block-to-tile map differs, so the two must agree bit for bit; a tile
+# visited twice or never would not. 16 and 24 tiles per plane use windows
+# (2 and 3 tiles each); 12 fall back to plane ranges.
+@pytest.mark.parametrize("shape,lines", [((64, 64, 24), 4), ((32, 96, 20), 4), ((64, 48, 9), 4)])
+def test_x_tile_orders_agree(gpu, shape, lines):
+    nx, ny, nz = shape
+    spec = W.GridSpec(nx, ny, nz, 1.0, 1.0, 0.8, W.tanh_faces(nz, 0.8, 1.5))
+    case = W.two_phase_case("xorder", spec, 1, 12, n_spheres=4)
+    g, f, rho, pp = oracle_inputs(case)
+    say(f"x tile orders {shape}, {ny // lines} tiles per plane")
+    out = {}
+    for prec in ("fp64", "mixed"):
+        plan = gpu.Plan(gpu.Grid.from_spec(spec), precision=prec)
+        for order in (1, 0):
+            plan.set_shape(lines_x=lines, lines_x_inv=lines, chunk_rows=4, x_staged=1, x_order=order)
+            out[prec, order] = host(plan.solve(dev(f), rho=dev(rho), p_prev=dev(pp)))
+        assert np.array_equal(out[prec, 0], out[prec, 1])
+    ps, _ = O.solve(f, g, rho, pp, with_relres=False)
+    assert rel_max_err(out["fp64", 1], ps[0]) <= TOL_FP64
